@@ -1,0 +1,183 @@
+"""Pins of the oracle's clover term and fermion force.
+
+Clover: A = 1 at U = 1, Hermitian, block-diagonal in chirality, gauge
+covariant, and the closed form of a constant abelian flux.  The overall sign
+of the clover term is a convention the paper does not fix (parity unpinned).
+
+Force: finite differences of the action S = phi^H (M^H M)^{-1} phi computed
+by dense solves (a route that never touches the oracle's force code), the
+identities Y = eta and S = |eta|^2 for phi = M^H eta, and gauge covariance."""
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+import oracle
+from oracle import dense
+from paper_2302_00850_amd.synth import Synth, bc_phases, unit_gauge
+from tests._util import rel
+
+ANTIPERIODIC = bc_phases((0, 0, 0, np.pi))
+GENERIC = bc_phases((0.3, -0.5, 0.7, np.pi))
+
+
+def test_clover_unit_gauge_is_identity():
+    dims = (4, 2, 2, 4)
+    A = oracle.clover(unit_gauge(dims).numpy(), 0.118, 1.0)
+    assert np.array_equal(A, np.broadcast_to(np.eye(12), A.shape))
+
+
+def test_clover_hermitian_and_chiral_blocks():
+    dims = (4, 4, 2, 2)
+    U = Synth(31).gauge(dims).numpy()
+    A = oracle.clover(U, 0.118, 1.0)
+    assert np.abs(A - A.conj().swapaxes(-1, -2)).max() < 1e-15
+    # gamma5 = diag(1,1,-1,-1) in spin: the (upper, lower) chiral blocks do not mix
+    assert np.abs(A[..., :6, 6:]).max() < 1e-15
+    assert np.abs(A[..., 6:, :6]).max() < 1e-15
+    # for these smooth fields each 6x6 block is positive definite
+    assert np.linalg.eigvalsh(A[..., :6, :6]).min() > 0
+    assert np.linalg.eigvalsh(A[..., 6:, 6:]).min() > 0
+
+
+def test_clover_gauge_covariance():
+    dims = (4, 2, 2, 4)
+    s = Synth(32)
+    U = s.gauge(dims).numpy()
+    G = s.haar_field(dims).numpy()
+    UG = np.empty_like(U)
+    for mu in range(4):
+        Gf = np.roll(G, -1, axis=3 - mu)
+        UG[..., mu, :, :] = G @ U[..., mu, :, :] @ Gf.conj().swapaxes(-1, -2)
+    A = oracle.clover(U, 0.118, 1.0)
+    AG = oracle.clover(UG, 0.118, 1.0)
+    # A(x) -> (1_spin (x) G(x)) A(x) (1_spin (x) G(x))^H
+    big = np.einsum("st,...ab->...satb", np.eye(4), G).reshape(G.shape[:4] + (12, 12))
+    expect = big @ A @ big.conj().swapaxes(-1, -2)
+    assert rel(AG, expect) < 1e-14
+
+
+def test_clover_constant_abelian_flux():
+    """U_x(x) = diag(e^{-i phi y}, e^{i phi y}, 1), other links 1, phi = 2 pi / Ly:
+    every x-y plaquette is diag(e^{i phi}, e^{-i phi}, 1), so
+    F_xy = sin(phi) diag(1, -1, 0), all other F vanish, and
+    A = 1 - kappa c_sw sin(phi) sigma_xy (x) diag(1, -1, 0)."""
+    dims = (4, 6, 2, 4)
+    lx, ly, lz, lt = dims
+    phi = 2 * np.pi / ly
+    U = unit_gauge(dims).numpy()
+    y = np.arange(ly)
+    U[:, :, :, :, 0, 0, 0] = np.exp(-1j * phi * y)[None, None, :, None]
+    U[:, :, :, :, 0, 1, 1] = np.exp(1j * phi * y)[None, None, :, None]
+    Fxy = oracle.field_strength(U, 0, 1)
+    np.testing.assert_allclose(Fxy, np.broadcast_to(np.sin(phi) * np.diag([1, -1, 0]), Fxy.shape),
+                               atol=1e-14)
+    for mu, nu in [(0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]:
+        assert np.abs(oracle.field_strength(U, mu, nu)).max() < 1e-14
+    kappa, csw = 0.118, 1.0
+    g = dense.gammas()
+    sig = 0.5j * (g[0] @ g[1] - g[1] @ g[0])
+    expect = np.eye(12) - kappa * csw * np.sin(phi) * np.kron(sig, np.diag([1, -1, 0]))
+    A = oracle.clover(U, kappa, csw)
+    np.testing.assert_allclose(A, np.broadcast_to(expect, A.shape), atol=1e-14)
+
+
+# ------------------------------------------------------------------- force
+
+def _solve_xy(U, phi, kappa, bc):
+    X, it, res = oracle.cg(U, phi, kappa, bc, system=0, tol=1e-14, max_iter=5000)
+    assert it > 0
+    return X, oracle.apply_M(U, X, kappa, bc)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    dims = (2, 2, 2, 4)
+    s = Synth(41)
+    U = s.gauge(dims).numpy()
+    phi = s.gaussian_spinor(dims)[0].numpy()
+    return U, phi, 0.12
+
+
+def test_force_grad_matches_dense_fd(tiny):
+    """G = dS/dRe U + i dS/dIm U against central differences of the dense action."""
+    U, phi, kappa = tiny
+    X, Y = _solve_xy(U, phi, kappa, GENERIC)
+    G = oracle.force(U, X, Y, kappa, GENERIC, mode=0)
+    rng = np.random.default_rng(0)
+    eps = 1e-5
+    worst = 0.0
+    for _ in range(12):
+        t, z, y, x = (rng.integers(n) for n in U.shape[:4])
+        mu, a, b = rng.integers(4), rng.integers(3), rng.integers(3)
+        d = []
+        for unit in (1.0, 1j):
+            Up, Um = U.copy(), U.copy()
+            Up[t, z, y, x, mu, a, b] += eps * unit
+            Um[t, z, y, x, mu, a, b] -= eps * unit
+            d.append((dense.action(Up, phi, kappa, GENERIC)
+                      - dense.action(Um, phi, kappa, GENERIC)) / (2 * eps))
+        fd = d[0] + 1j * d[1]
+        worst = max(worst, abs(fd - G[t, z, y, x, mu, a, b]))
+    assert worst < 1e-6 * np.abs(G).max()
+
+
+def _random_su3_generator(rng):
+    h = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+    h = 0.5 * (h + h.conj().T)
+    return h - np.trace(h) / 3 * np.eye(3)
+
+
+def test_force_lie_matches_dense_fd(tiny):
+    """dS/de for U_mu(x) -> exp(i e H) U_mu(x) equals Tr(H F); F Hermitian, traceless."""
+    U, phi, kappa = tiny
+    X, Y = _solve_xy(U, phi, kappa, GENERIC)
+    F = oracle.force(U, X, Y, kappa, GENERIC, mode=1)
+    assert np.abs(F - F.conj().swapaxes(-1, -2)).max() < 1e-13
+    assert np.abs(np.trace(F, axis1=-2, axis2=-1)).max() < 1e-13
+    rng = np.random.default_rng(1)
+    eps = 1e-5
+    for _ in range(8):
+        site = tuple(int(rng.integers(n)) for n in U.shape[:4])
+        mu = int(rng.integers(4))
+        H = _random_su3_generator(rng)
+        vals = []
+        for sgn in (1, -1):
+            Ue = U.copy()
+            Ue[site + (mu,)] = expm(1j * sgn * eps * H) @ U[site + (mu,)]
+            vals.append(dense.action(Ue, phi, kappa, GENERIC))
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        pred = np.trace(H @ F[site + (mu,)]).real
+        assert abs(fd - pred) < 1e-6 * max(1.0, abs(pred))
+
+
+def test_force_identities_phi_from_eta():
+    """phi = M^H eta gives Y = M X = eta and S = phi^H X = |eta|^2."""
+    dims = (4, 2, 2, 4)
+    s = Synth(42)
+    U = s.gauge(dims).numpy()
+    eta = s.gaussian_spinor(dims)[0].numpy()
+    kappa = 0.12
+    phi = oracle.apply_M(U, eta, kappa, ANTIPERIODIC, dagger=True)
+    X, Y = _solve_xy(U, phi, kappa, ANTIPERIODIC)
+    assert rel(Y, eta) < 1e-11
+    S = np.vdot(phi, X).real
+    assert abs(S - np.vdot(eta, eta).real) < 1e-11 * S
+
+
+def test_force_gauge_covariance():
+    dims = (4, 2, 2, 4)
+    s = Synth(43)
+    U = s.gauge(dims).numpy()
+    X = s.gaussian_spinor(dims)[0].numpy()
+    Y = s.gaussian_spinor(dims)[0].numpy()
+    G = s.haar_field(dims).numpy()
+    UG = np.empty_like(U)
+    for mu in range(4):
+        Gf = np.roll(G, -1, axis=3 - mu)
+        UG[..., mu, :, :] = G @ U[..., mu, :, :] @ Gf.conj().swapaxes(-1, -2)
+    XG = np.einsum("...ab,...sb->...sa", G, X)
+    YG = np.einsum("...ab,...sb->...sa", G, Y)
+    F = oracle.force(U, X, Y, 0.12, ANTIPERIODIC, mode=1)
+    FG = oracle.force(UG, XG, YG, 0.12, ANTIPERIODIC, mode=1)
+    expect = G[..., None, :, :] @ F @ G[..., None, :, :].conj().swapaxes(-1, -2)
+    assert rel(FG, expect) < 1e-13
