@@ -1,0 +1,221 @@
+/*
+ * cola.h -- C ABI of the MI355X (gfx950) Wilson-Dirac library.
+ *
+ * The library implements the data-parallel hot path of the CG fermion-matrix
+ * inverter that the paper (Kamleh, "Evolving the COLA software library",
+ * Lattice 2022) describes: the Wilson(-clover) Dirac operator applied to a
+ * fermion field ("fermion matrix"), conjugate-gradient solves with it in
+ * plain FP64 and in mixed precision (32-bit inner iterations, 64-bit outer
+ * solver), and the force term of Hybrid Monte Carlo.  The paper's GPU code is
+ * reached from Fortran through an ISO C binding; this header is the same kind
+ * of plain-C boundary: POD types, raw pointers, no C++ or torch types.
+ *
+ * Conventions (all entry points):
+ *   lattice   dims = {Lx, Ly, Lz, Lt}, all even and >= 2; mu = 0,1,2,3 = x,y,z,t;
+ *             site = x + Lx*(y + Ly*(z + Lz*t)); parity = (x+y+z+t) mod 2.
+ *   operator  (M psi)(x) = A(x) psi(x) - kappa sum_mu [ (1-g_mu) e+_mu(x) U_mu(x) psi(x+mu)
+ *                                                   + (1+g_mu) e-_mu(x) U_mu(x-mu)^H psi(x-mu) ]
+ *             chiral (DeGrand-Rossi) gammas; e+_mu(x) = bc_phase[mu] when x_mu = L_mu-1,
+ *             e-_mu(x) = conj(bc_phase[mu]) when x_mu = 0, else 1; A = 1 (csw = 0) or the
+ *             clover matrix 1 - kappa*csw*sum_{mu<nu} sigma_mu,nu F_mu,nu (csw != 0).
+ *             M^H = g5 M g5.
+ *   canonical complex128 (re, im interleaved) device arrays, row-major:
+ *             gauge  U[Lt][Lz][Ly][Lx][mu][row][col]
+ *             spinor psi[nrhs][Lt][Lz][Ly][Lx][spin][colour]
+ *   packed    the library's own per-parity structure-of-arrays form in one of the
+ *             precisions below (see cola_field_bytes); made by cola_pack_spinor.
+ *   streams   `stream` is a hipStream_t (NULL = default stream).  dslash_apply,
+ *             pack/unpack and fermion_force are asynchronous on it; set_gauge and
+ *             cg_solve synchronise it before returning.
+ *   ownership the caller owns every buffer passed in; the library owns its packed
+ *             gauge/clover copies and its workspace, released by cola_destroy.
+ *   errors    0 = COLA_OK; negative = nothing valid was produced (message in
+ *             cola_last_error); positive = output valid but flagged.
+ *   threads   a handle is not re-entrant: one handle per host thread / stream.
+ */
+#ifndef COLA_H
+#define COLA_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define COLA_ABI_VERSION 1
+
+/* status codes */
+enum {
+    COLA_OK = 0,
+    COLA_EINVAL = -1,       /* bad argument, unsupported combination, bad dims      */
+    COLA_EHIP = -2,         /* a HIP runtime call failed (text in cola_last_error)  */
+    COLA_ENOMEM = -3,       /* device allocation failed                             */
+    COLA_ESTATE = -4,       /* call out of order (e.g. no gauge field set)          */
+    COLA_NOT_CONVERGED = 1, /* cg: max_iter reached; x holds the last iterate       */
+    COLA_BREAKDOWN = 2      /* cg: NaN/Inf or a vanishing denominator               */
+};
+
+/* storage precision of packed fields: spinor format / link format */
+enum {
+    COLA_FP64 = 0,    /* FP64 spinors, FP64 links with all 18 reals               */
+    COLA_FP64_12 = 1, /* FP64 spinors, FP64 links, rows 0-1 stored (12 reals)     */
+    COLA_FP32 = 2,    /* FP32 spinors, FP32 links, 12 reals, FP32 arithmetic      */
+    COLA_FP16 = 3     /* FP16 spinors + one FP32 scale per site and rhs, FP16 links
+                         (12 reals), FP32 arithmetic                                */
+};
+
+/* operators for cola_dslash_apply */
+enum {
+    COLA_OP_HOP = 0,            /* out_p = D_{p,1-p} in_{1-p}  (half lattice, parity p)  */
+    COLA_OP_HOP_DAG = 1,        /* out_p = (D^H)_{p,1-p} in_{1-p}                        */
+    COLA_OP_M = 2,              /* full lattice M                                        */
+    COLA_OP_MDAG = 3,           /* full lattice M^H                                      */
+    COLA_OP_MDAGM = 4,          /* full lattice M^H M                                    */
+    COLA_OP_SCHUR = 5,          /* even sites: S = A_ee - kappa^2 D_eo A_oo^-1 D_oe      */
+    COLA_OP_SCHUR_DAG = 6,      /* S^H                                                   */
+    COLA_OP_SCHUR_DAGSCHUR = 7  /* S^H S                                                 */
+};
+
+/* linear systems for cola_cg_solve */
+enum {
+    COLA_SYS_MDAGM = 0,      /* M^H M x = b on the full lattice                         */
+    COLA_SYS_SCHUR = 1,      /* S^H S x_e = b_e on even sites (odd sites of x set to 0) */
+    COLA_SYS_PROPAGATOR = 2  /* M x = b, through S^H S on even sites + odd reconstruction */
+};
+
+/* solver schemes */
+enum {
+    COLA_CG_FP64 = 0,          /* plain FP64 CG                                        */
+    COLA_CG_FP32_RELIABLE = 1, /* FP32 CG, FP64 x accumulator, FP64 true residual every
+                                  reliable_interval iterations and at convergence       */
+    COLA_CG_FP16_DEFECT = 2,   /* FP64 defect correction around an FP16-storage inner CG */
+    COLA_CG_FP32_DEFECT = 3    /* FP64 defect correction around an FP32 inner CG         */
+};
+
+/* cola_create flags */
+enum {
+    COLA_FLAG_TIMING = 1u /* bracket every hop launch with HIP events (cola_get_stats) */
+};
+
+/* force modes */
+enum {
+    COLA_FORCE_GRAD = 0, /* G = dS/dRe U + i dS/dIm U                                  */
+    COLA_FORCE_LIE = 1   /* traceless Hermitian F with dS/de = Tr(H F), U -> e^{ieH} U  */
+};
+
+typedef struct cola_handle cola_handle_t;
+
+typedef struct {
+    int system;            /* COLA_SYS_*                                                */
+    int scheme;            /* COLA_CG_*                                                 */
+    int block;             /* 0: independent CG per column, batched (lockstep);
+                              1: block CG sharing one Krylov space (FP64 and defect inner) */
+    double tol;            /* stop when ||b - A x|| / ||b|| <= tol for every column,
+                              A the system's operator, checked in FP64                   */
+    int max_iter;          /* cap on (inner) iterations, summed over outer cycles       */
+    int reliable_interval; /* FP32_RELIABLE: iterations between FP64 residual updates   */
+    double inner_tol;      /* DEFECT: relative residual reduction of each inner solve   */
+    int use_x0;            /* 1: x holds the initial guess on entry                     */
+    int check_interval;    /* iterations between host convergence checks (0 = 8)        */
+} cola_cg_params_t;
+
+typedef struct {
+    int status;                /* COLA_OK, COLA_NOT_CONVERGED or COLA_BREAKDOWN         */
+    int iterations;            /* total (inner) CG iterations                          */
+    int outer_cycles;          /* defect-correction cycles                             */
+    int reliable_updates;      /* FP64 residual recomputations inside the solve         */
+    double *true_rel_residual; /* caller-owned host array[nrhs] (may be NULL): final
+                                  FP64 ||b - A x|| / ||b|| per column                   */
+    double seconds;            /* wall time of the solve                                */
+} cola_cg_result_t;
+
+/* Hop-kernel accounting, per storage precision (index COLA_FP64 .. COLA_FP16), filled
+ * only for handles created with COLA_FLAG_TIMING.  Algorithmic bytes count every
+ * link, input spinor and output spinor of a launch once (plus the epilogue's extra
+ * spinor / clover reads); flops count 1320 per site and rhs, 42 per rebuilt link
+ * row, 48 per axpy and 552 per clover application. */
+typedef struct {
+    long long hop_launches[4]; /* hop kernels launched                                */
+    double hop_seconds[4];     /* summed HIP-event durations, on the launch stream     */
+    double hop_bytes[4];       /* summed algorithmic bytes                             */
+    double hop_flops[4];       /* summed flops                                         */
+} cola_stats_t;
+
+/* ---------------------------------------------------------------- lifecycle */
+
+int cola_abi_version(void);
+
+/* Create a handle on the current HIP device.  dims: {Lx,Ly,Lz,Lt}, all even, >= 2.
+ * bc_phase: 8 doubles, (re, im) of e^{i theta_mu} for mu = 0..3 (antiperiodic time:
+ * {1,0, 1,0, 1,0, -1,0}).  csw = 0 selects plain Wilson.  Returns COLA_EINVAL for
+ * bad dims, a null h or non-finite kappa/csw. */
+int cola_create(cola_handle_t **h, const int dims[4], double kappa, const double bc_phase[8],
+                double csw, unsigned flags);
+int cola_destroy(cola_handle_t *h);
+/* Text of the last error on h (empty string if none; never NULL). */
+const char *cola_last_error(const cola_handle_t *h);
+
+/* ------------------------------------------------------------------- fields */
+
+/* Copy in the gauge field (canonical complex128 device array) and build every
+ * packed form (FP64 18-real; 12-real FP64/FP32/FP16 when every link is SU(3) to
+ * 1e-12) plus the clover blocks and their inverses when csw != 0.  Synchronises
+ * `stream`.  Compressed precisions are refused later (COLA_EINVAL) if the field
+ * is not SU(3).  The canonical array is not retained. */
+int cola_set_gauge(cola_handle_t *h, const void *U_dev, void *stream);
+
+/* 1 when the current gauge field passed the SU(3) check (12-real forms usable). */
+int cola_gauge_is_su3(const cola_handle_t *h);
+
+/* Bytes of a packed spinor field of precision `prec` with nrhs right-hand sides on
+ * one parity (parity 0 or 1) or on the full lattice (parity -1).  0 on bad args. */
+size_t cola_field_bytes(const cola_handle_t *h, int prec, int nrhs, int parity);
+
+/* canonical complex128 [nrhs][Lt][Lz][Ly][Lx][4][3] <-> packed.  parity -1 packs the
+ * full lattice; parity 0/1 packs only that parity's sites (unpack of one parity
+ * leaves the other parity's sites of dst untouched).  FP16 rounds to nearest even
+ * after dividing by the per-site, per-rhs max |component|. */
+int cola_pack_spinor(cola_handle_t *h, void *dst_packed, const void *src_canon, int prec,
+                     int nrhs, int parity, void *stream);
+int cola_unpack_spinor(cola_handle_t *h, void *dst_canon, const void *src_packed, int prec,
+                       int nrhs, int parity, void *stream);
+
+/* -------------------------------------------------------------- hot path */
+
+/* out = op(in) on packed fields of precision `prec` with nrhs right-hand sides.
+ * HOP/HOP_DAG: in is the parity (1-parity) block, out the `parity` block.
+ * M/MDAG/MDAGM: full-lattice fields.  SCHUR*: even-parity blocks (parity ignored).
+ * out and in must not overlap.  Asynchronous on `stream`. */
+int cola_dslash_apply(cola_handle_t *h, void *out, const void *in, int op, int parity, int prec,
+                      int nrhs, void *stream);
+
+/* Solve for nrhs right-hand sides; x and b are canonical complex128 device arrays
+ * [nrhs][Lt][Lz][Ly][Lx][4][3].  For COLA_SYS_SCHUR only the even sites of b are
+ * read and the odd sites of x are set to zero.  Synchronises `stream`.  Returns
+ * COLA_OK, COLA_NOT_CONVERGED (x = best iterate) or COLA_BREAKDOWN, or < 0. */
+int cola_cg_solve(cola_handle_t *h, void *x, const void *b, int nrhs, const cola_cg_params_t *p,
+                  cola_cg_result_t *r, void *stream);
+
+/* Fermion force of S = phi^H (M^H M)^{-1} phi for plain Wilson M, from X = (M^H M)^{-1} phi
+ * and Y = M X (canonical complex128 spinors, nrhs = 1).  F: canonical gauge-shaped
+ * complex128 output [Lt][Lz][Ly][Lx][4][3][3].  COLA_EINVAL when csw != 0 (the clover
+ * term's own force is not implemented).  Asynchronous on `stream`. */
+int cola_fermion_force(cola_handle_t *h, void *F_dev, const void *X_dev, const void *Y_dev,
+                       int mode, void *stream);
+
+/* ---------------------------------------------------------- diagnostics */
+
+int cola_get_stats(cola_handle_t *h, cola_stats_t *s); /* synchronises pending timings */
+int cola_reset_stats(cola_handle_t *h);
+
+/* Autotuning of the hop launch shape (threads per block, rhs per thread, grid).
+ * mode 0: off (defaults), 1: tune on first use of a key, 2: re-tune every key.
+ * The table is kept per handle; cola_tune_dump writes it as JSON text into buf
+ * (returns the length needed, including the terminating NUL). */
+int cola_set_tuning(cola_handle_t *h, int mode);
+size_t cola_tune_dump(const cola_handle_t *h, char *buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COLA_H */

@@ -34,6 +34,8 @@ def _load():
         build()
     lib = ctypes.CDLL(_LIB_PATH)
     lib.oracle_hop.argtypes = [_ip, _dp, _dp, _dp, _dp, ctypes.c_int]
+    lib.oracle_hop_sites.argtypes = [_ip, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_long),
+                                     ctypes.c_long, _dp, ctypes.c_int]
     lib.oracle_apply_M.argtypes = [_ip, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
     lib.oracle_apply_schur.argtypes = [_ip, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp,
                                        ctypes.c_int]
@@ -103,6 +105,17 @@ def hop(U, psi, bc, dagger=False):
         lib.oracle_hop(L, _ptr(b), _ptr(U), _ptr(p), _ptr(out), int(dagger))
         return out
     return _per_rhs(one, psi, U.shape[:4] + (4, 3))
+
+
+def hop_sites(U, psi, bc, sites, dagger=False):
+    """(D psi) at the given lexicographic site indices only, shape (n, 4, 3)."""
+    U, psi, b = _arr(U), _arr(psi), _bc(bc)
+    s = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
+    out = np.empty((len(s), 4, 3), dtype=np.complex128)
+    _load().oracle_hop_sites(_dims(U), _ptr(b), _ptr(U), _ptr(psi),
+                             s.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), len(s), _ptr(out),
+                             int(dagger))
+    return out
 
 
 def apply_M(U, psi, kappa, bc, clover=None, dagger=False):

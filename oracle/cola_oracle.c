@@ -84,12 +84,10 @@ static const cplx *link(const cplx *U, long s, int mu) { return U + (s * 4 + mu)
  * out(x) = sum_mu [ (1 + sg g_mu) e+ U_mu(x) in(x+mu) + (1 - sg g_mu) e- U_mu(x-mu)^H in(x-mu) ]
  * with sg = -1 for D and sg = +1 for D^H = g5 D g5 (dagger != 0).
  */
-static void hop(const int L[4], const double *bc, const cplx *U, const cplx *in, cplx *out,
-                int dagger) {
-    const long V = volume(L);
+static void hop_site(const int L[4], const double *bc, const cplx *U, const cplx *in, long s,
+                     cplx *out, int dagger) {
     const double sg = dagger ? 1.0 : -1.0;
-#pragma omp parallel for schedule(static)
-    for (long s = 0; s < V; ++s) {
+    {
         int x[4];
         site_coords(L, s, x);
         cplx acc[12];
@@ -130,8 +128,15 @@ static void hop(const int L[4], const double *bc, const cplx *U, const cplx *in,
                     acc[sp * 3 + a] += eb * (chi[sp * 3 + a] - sg * g);
                 }
         }
-        for (int k = 0; k < 12; ++k) out[s * 12 + k] = acc[k];
+        for (int k = 0; k < 12; ++k) out[k] = acc[k];
     }
+}
+
+static void hop(const int L[4], const double *bc, const cplx *U, const cplx *in, cplx *out,
+                int dagger) {
+    const long V = volume(L);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; ++s) hop_site(L, bc, U, in, s, out + s * 12, dagger);
 }
 
 /* out(x) = C(x) in(x) for a per-site 12x12 matrix field C (identity if C == NULL) */
@@ -163,6 +168,14 @@ static void mask_parity(const int L[4], cplx *f, int keep) {
 void oracle_hop(const int L[4], const double *bc, const double *U, const double *in, double *out,
                 int dagger) {
     hop(L, bc, (const cplx *)U, (const cplx *)in, (cplx *)out, dagger);
+}
+
+/* the hopping term at a list of sites only: out[k*12 ..] = (D in)(sites[k]) */
+void oracle_hop_sites(const int L[4], const double *bc, const double *U, const double *in,
+                      const long *sites, long n, double *out, int dagger) {
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k)
+        hop_site(L, bc, (const cplx *)U, (const cplx *)in, sites[k], (cplx *)out + k * 12, dagger);
 }
 
 /* M psi = A psi - kappa D psi; M^H = A - kappa D^H since A is Hermitian. */

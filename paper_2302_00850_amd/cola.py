@@ -1,0 +1,349 @@
+"""ctypes binding of libcola.so (include/cola.h).
+
+The module-level functions carry the C names and only marshal arguments:
+device buffers are passed as integer addresses (``tensor.data_ptr()``), the
+stream as ``torch.cuda.current_stream().cuda_stream``.  Every computation runs
+in the HIP library; there is no fallback path.  ``Lattice`` is a thin
+convenience layer over the same calls, with torch tensors supplying device
+memory; ``PseudofermionAction`` exposes the fermion action and its force to
+torch autograd.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcola.so")
+
+# ---- constants mirrored from include/cola.h
+COLA_OK, COLA_EINVAL, COLA_EHIP, COLA_ENOMEM, COLA_ESTATE = 0, -1, -2, -3, -4
+COLA_NOT_CONVERGED, COLA_BREAKDOWN = 1, 2
+COLA_FP64, COLA_FP64_12, COLA_FP32, COLA_FP16 = 0, 1, 2, 3
+(COLA_OP_HOP, COLA_OP_HOP_DAG, COLA_OP_M, COLA_OP_MDAG, COLA_OP_MDAGM, COLA_OP_SCHUR,
+ COLA_OP_SCHUR_DAG, COLA_OP_SCHUR_DAGSCHUR) = range(8)
+COLA_SYS_MDAGM, COLA_SYS_SCHUR, COLA_SYS_PROPAGATOR = 0, 1, 2
+COLA_CG_FP64, COLA_CG_FP32_RELIABLE, COLA_CG_FP16_DEFECT, COLA_CG_FP32_DEFECT = 0, 1, 2, 3
+COLA_FLAG_TIMING = 1
+COLA_FORCE_GRAD, COLA_FORCE_LIE = 0, 1
+MAX_RHS = 16
+
+
+class ColaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cola error {code}: {msg}")
+        self.code = code
+
+
+class CgParams(ctypes.Structure):
+    _fields_ = [("system", ctypes.c_int), ("scheme", ctypes.c_int), ("block", ctypes.c_int),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("reliable_interval", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("use_x0", ctypes.c_int), ("check_interval", ctypes.c_int)]
+
+
+class CgResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int),
+                ("outer_cycles", ctypes.c_int), ("reliable_updates", ctypes.c_int),
+                ("true_rel_residual", ctypes.POINTER(ctypes.c_double)),
+                ("seconds", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("hop_launches", ctypes.c_longlong * 4), ("hop_seconds", ctypes.c_double * 4),
+                ("hop_bytes", ctypes.c_double * 4), ("hop_flops", ctypes.c_double * 4)]
+
+
+EXPORTS = ["cola_abi_version", "cola_create", "cola_destroy", "cola_last_error", "cola_set_gauge",
+           "cola_gauge_is_su3", "cola_field_bytes", "cola_pack_spinor", "cola_unpack_spinor",
+           "cola_dslash_apply", "cola_cg_solve", "cola_fermion_force", "cola_get_stats",
+           "cola_reset_stats", "cola_set_tuning", "cola_tune_dump"]
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with `python -m paper_2302_00850_amd.build`")
+    lib = ctypes.CDLL(path)
+    lib.cola_abi_version.restype = ctypes.c_int
+    lib.cola_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int), ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_uint]
+    lib.cola_destroy.argtypes = [_vp]
+    lib.cola_last_error.argtypes = [_vp]
+    lib.cola_last_error.restype = ctypes.c_char_p
+    lib.cola_set_gauge.argtypes = [_vp, _vp, _vp]
+    lib.cola_gauge_is_su3.argtypes = [_vp]
+    lib.cola_field_bytes.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.cola_field_bytes.restype = ctypes.c_size_t
+    lib.cola_pack_spinor.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]
+    lib.cola_unpack_spinor.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]
+    lib.cola_dslash_apply.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, _vp]
+    lib.cola_cg_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(CgParams),
+                                  ctypes.POINTER(CgResult), _vp]
+    lib.cola_fermion_force.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, _vp]
+    lib.cola_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
+    lib.cola_reset_stats.argtypes = [_vp]
+    lib.cola_set_tuning.argtypes = [_vp, ctypes.c_int]
+    lib.cola_tune_dump.argtypes = [_vp, ctypes.c_char_p, ctypes.c_size_t]
+    lib.cola_tune_dump.restype = ctypes.c_size_t
+    _lib = lib
+    return lib
+
+
+def _check(h, rc):
+    if rc < 0:
+        msg = load().cola_last_error(h).decode() if h else ""
+        raise ColaError(rc, msg)
+    return rc
+
+
+# ------------------------------------------------------------- C-named calls
+
+def cola_abi_version() -> int:
+    return load().cola_abi_version()
+
+
+def cola_create(dims, kappa, bc_phase, csw=0.0, flags=0):
+    d = (ctypes.c_int * 4)(*[int(v) for v in dims])
+    ph = (ctypes.c_double * 8)(*np.asarray(bc_phase, dtype=np.float64).reshape(8))
+    h = _vp()
+    rc = load().cola_create(ctypes.byref(h), d, float(kappa), ph, float(csw), int(flags))
+    if rc != COLA_OK:
+        raise ColaError(rc, "cola_create failed (dims must be even and >= 2)")
+    return h
+
+
+def cola_destroy(h):
+    return load().cola_destroy(h)
+
+
+def cola_last_error(h) -> str:
+    return load().cola_last_error(h).decode()
+
+
+def cola_set_gauge(h, U_ptr, stream=None):
+    return _check(h, load().cola_set_gauge(h, U_ptr, stream))
+
+
+def cola_gauge_is_su3(h) -> int:
+    return load().cola_gauge_is_su3(h)
+
+
+def cola_field_bytes(h, prec, nrhs, parity) -> int:
+    return load().cola_field_bytes(h, prec, nrhs, parity)
+
+
+def cola_pack_spinor(h, dst, src, prec, nrhs, parity, stream=None):
+    return _check(h, load().cola_pack_spinor(h, dst, src, prec, nrhs, parity, stream))
+
+
+def cola_unpack_spinor(h, dst, src, prec, nrhs, parity, stream=None):
+    return _check(h, load().cola_unpack_spinor(h, dst, src, prec, nrhs, parity, stream))
+
+
+def cola_dslash_apply(h, out, inp, op, parity, prec, nrhs, stream=None):
+    return _check(h, load().cola_dslash_apply(h, out, inp, op, parity, prec, nrhs, stream))
+
+
+def cola_cg_solve(h, x, b, nrhs, params: CgParams, result: CgResult, stream=None):
+    return _check(h, load().cola_cg_solve(h, x, b, nrhs, ctypes.byref(params),
+                                          ctypes.byref(result), stream))
+
+
+def cola_fermion_force(h, F, X, Y, mode, stream=None):
+    return _check(h, load().cola_fermion_force(h, F, X, Y, mode, stream))
+
+
+def cola_get_stats(h) -> Stats:
+    s = Stats()
+    _check(h, load().cola_get_stats(h, ctypes.byref(s)))
+    return s
+
+
+def cola_reset_stats(h):
+    return _check(h, load().cola_reset_stats(h))
+
+
+def cola_set_tuning(h, mode):
+    return _check(h, load().cola_set_tuning(h, mode))
+
+
+def cola_tune_dump(h) -> str:
+    n = load().cola_tune_dump(h, None, 0)
+    buf = ctypes.create_string_buffer(n)
+    load().cola_tune_dump(h, buf, n)
+    return buf.value.decode()
+
+
+# ------------------------------------------------------------- convenience
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: torch.Tensor) -> int:
+    if not t.is_cuda:
+        raise ValueError("device tensor required")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor required")
+    return t.data_ptr()
+
+
+class Lattice:
+    """A handle bound to a lattice shape, kappa, boundary phases and c_sw."""
+
+    def __init__(self, dims, kappa, bc_phase, csw=0.0, flags=0):
+        self.dims = tuple(int(v) for v in dims)
+        self.kappa = float(kappa)
+        self.bc_phase = np.asarray(bc_phase, dtype=np.float64).reshape(4, 2)
+        self.csw = float(csw)
+        self.h = cola_create(self.dims, self.kappa, self.bc_phase, self.csw, flags)
+        lx, ly, lz, lt = self.dims
+        self.site_shape = (lt, lz, ly, lx)
+
+    def close(self):
+        if self.h:
+            cola_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # fields
+    def set_gauge(self, U: torch.Tensor):
+        if U.dtype != torch.complex128 or tuple(U.shape) != self.site_shape + (4, 3, 3):
+            raise ValueError("gauge field must be complex128 (Lt,Lz,Ly,Lx,4,3,3)")
+        cola_set_gauge(self.h, _ptr(U), _stream())
+
+    @property
+    def gauge_is_su3(self) -> bool:
+        return bool(cola_gauge_is_su3(self.h))
+
+    def empty_packed(self, prec, nrhs=1, parity=-1) -> torch.Tensor:
+        n = cola_field_bytes(self.h, prec, nrhs, parity)
+        if n == 0:
+            raise ValueError("bad precision / nrhs / parity")
+        return torch.zeros(n, dtype=torch.uint8, device="cuda")
+
+    def _spinor_rhs(self, psi: torch.Tensor) -> int:
+        """Validate a canonical spinor tensor; returns its number of right-hand sides."""
+        if psi.dtype != torch.complex128 or not psi.is_cuda:
+            raise ValueError("spinor must be a complex128 device tensor")
+        shape = tuple(psi.shape)
+        if shape == self.site_shape + (4, 3):
+            return 1
+        if len(shape) == 7 and shape[1:] == self.site_shape + (4, 3) and 1 <= shape[0] <= MAX_RHS:
+            return shape[0]
+        raise ValueError(f"spinor shape {shape} does not match (nrhs,)+{self.site_shape}+(4,3)")
+
+    def _packed_ok(self, t: torch.Tensor, prec, nrhs, parity):
+        need = cola_field_bytes(self.h, prec, nrhs, parity)
+        if need == 0 or t.dtype != torch.uint8 or not t.is_cuda or t.numel() < need:
+            raise ValueError(f"packed buffer must be a device uint8 tensor of >= {need} bytes")
+
+    def pack(self, psi: torch.Tensor, prec, parity=-1) -> torch.Tensor:
+        nrhs = self._spinor_rhs(psi)
+        out = self.empty_packed(prec, nrhs, parity)
+        cola_pack_spinor(self.h, _ptr(out), _ptr(psi.contiguous()), prec, nrhs, parity, _stream())
+        return out
+
+    def unpack(self, packed: torch.Tensor, prec, nrhs=1, parity=-1, out=None) -> torch.Tensor:
+        self._packed_ok(packed, prec, nrhs, parity)
+        if out is None:
+            out = torch.zeros((nrhs,) + self.site_shape + (4, 3), dtype=torch.complex128,
+                              device="cuda")
+        if self._spinor_rhs(out) != nrhs:
+            raise ValueError("out has the wrong number of right-hand sides")
+        cola_unpack_spinor(self.h, _ptr(out), _ptr(packed), prec, nrhs, parity, _stream())
+        return out
+
+    def dslash(self, out: torch.Tensor, inp: torch.Tensor, op, parity=-1, prec=COLA_FP64, nrhs=1):
+        full = op in (COLA_OP_M, COLA_OP_MDAG, COLA_OP_MDAGM)
+        if nrhs < 1 or nrhs > MAX_RHS or prec not in (0, 1, 2, 3):
+            # let the library report the error without touching the buffers
+            cola_dslash_apply(self.h, _ptr(out), _ptr(inp), op, parity, prec, nrhs, _stream())
+        self._packed_ok(out, prec, nrhs, -1 if full else 0)
+        self._packed_ok(inp, prec, nrhs, -1 if full else 0)
+        cola_dslash_apply(self.h, _ptr(out), _ptr(inp), op, parity, prec, nrhs, _stream())
+        return out
+
+    def cg(self, b: torch.Tensor, system=COLA_SYS_MDAGM, scheme=COLA_CG_FP64, tol=1e-10,
+           max_iter=20000, reliable_interval=50, inner_tol=0.0, x0=None, check_interval=0,
+           block=0):
+        nrhs = self._spinor_rhs(b)
+        if x0 is not None and tuple(x0.shape) != tuple(b.shape):
+            raise ValueError("x0 must have the shape of b")
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        p = CgParams(system, scheme, block, tol, max_iter, reliable_interval, inner_tol,
+                     0 if x0 is None else 1, check_interval)
+        res = (ctypes.c_double * nrhs)()
+        r = CgResult(0, 0, 0, 0, ctypes.cast(res, ctypes.POINTER(ctypes.c_double)), 0.0)
+        cola_cg_solve(self.h, _ptr(x), _ptr(b.contiguous()), nrhs, p, r, _stream())
+        info = {"status": r.status, "iterations": r.iterations, "outer_cycles": r.outer_cycles,
+                "reliable_updates": r.reliable_updates, "true_rel_residual": list(res),
+                "seconds": r.seconds}
+        return x, info
+
+    def force(self, X: torch.Tensor, Y: torch.Tensor, mode=COLA_FORCE_GRAD) -> torch.Tensor:
+        if self._spinor_rhs(X) != 1 or self._spinor_rhs(Y) != 1:
+            raise ValueError("force takes single-rhs X and Y")
+        F = torch.empty(self.site_shape + (4, 3, 3), dtype=torch.complex128, device="cuda")
+        cola_fermion_force(self.h, _ptr(F), _ptr(X.contiguous()), _ptr(Y.contiguous()), mode,
+                           _stream())
+        return F
+
+    def stats(self, prec=None) -> dict:
+        """Hop accounting for one precision, or summed over all when prec is None."""
+        s = cola_get_stats(self.h)
+        idx = range(4) if prec is None else [prec]
+        return {"hop_launches": sum(s.hop_launches[i] for i in idx),
+                "hop_seconds": sum(s.hop_seconds[i] for i in idx),
+                "hop_bytes": sum(s.hop_bytes[i] for i in idx),
+                "hop_flops": sum(s.hop_flops[i] for i in idx)}
+
+    def reset_stats(self):
+        cola_reset_stats(self.h)
+
+
+class PseudofermionAction(torch.autograd.Function):
+    """S(U) = phi^H (M^H M)^{-1} phi for plain Wilson M; backward gives dS/dU.
+
+    forward: X = (M^H M)^{-1} phi by FP64 CG, Y = M X, S = Re <phi, X>.
+    backward: grad_U = gS * (dS/dRe U + i dS/dIm U) from the link-wise adjoint
+    kernel; phi receives no gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, U, phi, lattice: Lattice, tol=1e-12):
+        lattice.set_gauge(U.detach())
+        X, info = lattice.cg(phi.detach().reshape((1,) + lattice.site_shape + (4, 3)),
+                             system=COLA_SYS_MDAGM, scheme=COLA_CG_FP64, tol=tol)
+        if info["status"] != COLA_OK:
+            raise ColaError(info["status"], f"CG did not converge: {info}")
+        X = X.reshape(phi.shape)
+        packed = lattice.pack(X, COLA_FP64, -1)
+        Yp = torch.zeros_like(packed)
+        lattice.dslash(Yp, packed, COLA_OP_M, -1, COLA_FP64, 1)
+        Y = lattice.unpack(Yp, COLA_FP64, 1, -1).reshape(phi.shape)
+        ctx.lattice = lattice
+        ctx.save_for_backward(X, Y)
+        return torch.vdot(phi.detach().reshape(-1), X.reshape(-1)).real
+
+    @staticmethod
+    def backward(ctx, gS):
+        X, Y = ctx.saved_tensors
+        G = ctx.lattice.force(X, Y, COLA_FORCE_GRAD)
+        return gS * G, None, None, None

@@ -1,0 +1,358 @@
+// Site-structured vector kernels for the CG solvers.  One lane owns one
+// (site, rhs) pair and all 12 of its spin-colour components, so FP16 blocks
+// can rescale per site and every per-rhs scalar (alpha, beta, scale) is one
+// register.  Consecutive lanes take consecutive (site, rhs) pairs, which in
+// the rhs-innermost packed layout are consecutive addresses for every
+// component.  Reductions are per rhs, in FP64, deterministic.
+#include "device.h"
+#include "launch.h"
+
+namespace cola {
+
+namespace {
+
+size_t block_bytes(SpinorFmt f, int S, int R) {
+    const size_t SR = (size_t)S * R;
+    switch (f) {
+        case SpinorFmt::F64: return 12 * SR * 16;
+        case SpinorFmt::F32: return 12 * SR * 8;
+        default: return 12 * SR * 4 + SR * 4;
+    }
+}
+
+struct Loc {
+    uint32_t blk, i, r;
+};
+
+template <SpinorFmt F>
+__device__ __forceinline__ SpinorBlock<F> view(const void *base, size_t bb, const Loc &l, int S,
+                                               int R) {
+    return SpinorBlock<F>((const char *)base + l.blk * bb, S, R);
+}
+
+// Generic grid-stride driver: f(loc) returns this lane's contribution to the
+// per-rhs reduction (ignored when red.result is null).
+template <class Fn>
+__global__ void __launch_bounds__(256) site_kernel(Fn f, const BlasShape sh, const Reduce red) {
+    extern __shared__ double lds[];
+    const uint32_t SR = (uint32_t)sh.S * sh.R;
+    const uint32_t total = SR * (uint32_t)sh.nblk;
+    double acc[1] = {0.0};
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += gridDim.x * blockDim.x) {
+        Loc l;
+        l.blk = t / SR;
+        const uint32_t e = t - l.blk * SR;
+        l.i = e / (uint32_t)sh.R;
+        l.r = e - l.i * (uint32_t)sh.R;
+        acc[0] += f(l);
+    }
+    if (red.result) {
+        const int slot = threadIdx.x / sh.R;
+        const int q = threadIdx.x - slot * sh.R;
+        block_sum_to_result<1>(lds, sh.T, sh.R, slot, q, 1, acc, red.partial, red.counter,
+                               red.result);
+    }
+}
+
+template <class Fn>
+hipError_t run(const Fn &f, const BlasShape &sh, const Reduce *red, hipStream_t st) {
+    Reduce r = red ? *red : Reduce{nullptr, nullptr, nullptr};
+    const size_t shm = r.result ? (size_t)sh.T * sh.R * sizeof(double) : 0;
+    hipLaunchKernelGGL(site_kernel<Fn>, dim3(sh.grid), dim3(sh.T * sh.R), shm, st, f, sh, r);
+    return hipGetLastError();
+}
+
+template <SpinorFmt FX, SpinorFmt FP, SpinorFmt FR, SpinorFmt FA>
+struct XrFn {
+    void *x;
+    const void *p;
+    void *r;
+    const void *ap;
+    size_t bx, bp, br, ba;
+    const double *rho, *pi, *pi2;
+    const int *active;
+    int S, R;
+    __device__ double operator()(const Loc &l) const {
+        using TX = typename SpinorT<FX>::real;
+        using TR = typename SpinorT<FR>::real;
+        const double den = pi[l.r] + (pi2 ? pi2[l.r] : 0.0);
+        const double al = active[l.r] && den != 0.0 ? rho[l.r] / den : 0.0;
+        const auto X = view<FX>(x, bx, l, S, R);
+        const auto P = view<FP>(p, bp, l, S, R);
+        const auto Rv = view<FR>(r, br, l, S, R);
+        const auto A = view<FA>(ap, ba, l, S, R);
+        cpx<TX> xv[12];
+        cpx<typename SpinorT<FP>::real> pv[12];
+        cpx<TR> rv[12];
+        cpx<typename SpinorT<FA>::real> av[12];
+        X.load(l.i, l.r, xv);
+        P.load(l.i, l.r, pv);
+        Rv.load(l.i, l.r, rv);
+        A.load(l.i, l.r, av);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            xv[c].x += (TX)al * (TX)pv[c].x;
+            xv[c].y += (TX)al * (TX)pv[c].y;
+            rv[c].x -= (TR)al * (TR)av[c].x;
+            rv[c].y -= (TR)al * (TR)av[c].y;
+        }
+        X.store(l.i, l.r, xv);
+        Rv.store(l.i, l.r, rv);
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) s += (double)norm2(rv[c]);
+        return s;
+    }
+};
+
+template <SpinorFmt FR, SpinorFmt FP>
+struct PFn {
+    const void *r;
+    void *p;
+    size_t br, bp;
+    const double *rho_new, *rho;
+    const int *active;
+    int S, R;
+    __device__ double operator()(const Loc &l) const {
+        using TP = typename SpinorT<FP>::real;
+        const double be = active[l.r] && rho[l.r] != 0.0 ? rho_new[l.r] / rho[l.r] : 0.0;
+        const auto Rv = view<FR>(r, br, l, S, R);
+        const auto P = view<FP>(p, bp, l, S, R);
+        cpx<typename SpinorT<FR>::real> rv[12];
+        cpx<TP> pv[12];
+        Rv.load(l.i, l.r, rv);
+        P.load(l.i, l.r, pv);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            pv[c].x = (TP)rv[c].x + (TP)be * pv[c].x;
+            pv[c].y = (TP)rv[c].y + (TP)be * pv[c].y;
+        }
+        P.store(l.i, l.r, pv);
+        return 0.0;
+    }
+};
+
+template <SpinorFmt F>
+struct NormFn {
+    const void *v;
+    size_t bv;
+    int S, R;
+    __device__ double operator()(const Loc &l) const {
+        cpx<typename SpinorT<F>::real> a[12];
+        view<F>(v, bv, l, S, R).load(l.i, l.r, a);
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) s += (double)norm2(a[c]);
+        return s;
+    }
+};
+
+template <SpinorFmt FD, SpinorFmt FS>
+struct ConvFn {
+    void *d;
+    const void *s;
+    size_t bd, bs;
+    const double *scale;
+    int inv;
+    int S, R;
+    __device__ double operator()(const Loc &l) const {
+        using TD = typename SpinorT<FD>::real;
+        cpx<typename SpinorT<FS>::real> a[12];
+        view<FS>(s, bs, l, S, R).load(l.i, l.r, a);
+        double f = 1.0;
+        if (scale) f = inv ? (scale[l.r] != 0.0 ? 1.0 / scale[l.r] : 0.0) : scale[l.r];
+        cpx<TD> o[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) o[c] = {(TD)(f * (double)a[c].x), (TD)(f * (double)a[c].y)};
+        view<FD>(d, bd, l, S, R).store(l.i, l.r, o);
+        double n = 0.0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) n += (double)norm2(o[c]);
+        return n;
+    }
+};
+
+template <SpinorFmt FS>
+struct AccumFn {
+    void *d;
+    void *s;
+    size_t bd, bs;
+    const double *scale;
+    int zero;
+    int S, R;
+    __device__ double operator()(const Loc &l) const {
+        using TS = typename SpinorT<FS>::real;
+        const auto Sv = view<FS>(s, bs, l, S, R);
+        const auto D = view<SpinorFmt::F64>(d, bd, l, S, R);
+        cpx<TS> a[12];
+        cpx<double> o[12];
+        Sv.load(l.i, l.r, a);
+        D.load(l.i, l.r, o);
+        const double f = scale ? scale[l.r] : 1.0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            o[c].x = fma(f, (double)a[c].x, o[c].x);
+            o[c].y = fma(f, (double)a[c].y, o[c].y);
+        }
+        D.store(l.i, l.r, o);
+        if (zero) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) a[c] = {(TS)0, (TS)0};
+            Sv.store(l.i, l.r, a);
+        }
+        return 0.0;
+    }
+};
+
+struct ResidualFn {
+    void *r;
+    const void *b, *ax;
+    size_t bb;
+    int S, R;
+    __device__ double operator()(const Loc &l) const {
+        cpx<double> bv[12], av[12];
+        view<SpinorFmt::F64>(b, bb, l, S, R).load(l.i, l.r, bv);
+        view<SpinorFmt::F64>(ax, bb, l, S, R).load(l.i, l.r, av);
+        double n = 0.0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            bv[c] = bv[c] - av[c];
+            n += norm2(bv[c]);
+        }
+        view<SpinorFmt::F64>(r, bb, l, S, R).store(l.i, l.r, bv);
+        return n;
+    }
+};
+
+template <SpinorFmt F, typename CR>
+struct CloverFn {
+    void *out;
+    const void *in;
+    const void *clov;
+    size_t bb;
+    int parity;
+    int S, R;
+    __device__ double operator()(const Loc &l) const {
+        using T = typename SpinorT<F>::real;
+        cpx<T> a[12], o[12];
+        view<F>(in, bb, l, S, R).load(l.i, l.r, a);
+        clover_apply<CR, T>(clov, S, parity, l.i, a, o);
+        view<F>(out, bb, l, S, R).store(l.i, l.r, o);
+        return 0.0;
+    }
+};
+
+}  // namespace
+
+BlasShape blas_shape(const Geom &g, int nrhs, int nblk) {
+    BlasShape b;
+    b.S = g.S;
+    b.R = nrhs;
+    b.nblk = nblk;
+    int T = 1;
+    while (T * 2 * nrhs <= 256) T *= 2;
+    b.T = T;
+    const size_t work = (size_t)g.S * nrhs * nblk;
+    size_t grid = (work + (size_t)T * nrhs - 1) / ((size_t)T * nrhs);
+    if (grid > 8192) grid = 8192;
+    b.grid = (int)(grid < 1 ? 1 : grid);
+    return b;
+}
+
+#define DISPATCH_FMT(f, FT, ...)                                     \
+    switch (f) {                                                     \
+        case SpinorFmt::F64: { constexpr SpinorFmt FT = SpinorFmt::F64; __VA_ARGS__; } break; \
+        case SpinorFmt::F32: { constexpr SpinorFmt FT = SpinorFmt::F32; __VA_ARGS__; } break; \
+        case SpinorFmt::F16: { constexpr SpinorFmt FT = SpinorFmt::F16; __VA_ARGS__; } break; \
+    }
+
+hipError_t launch_cg_xr(const BlasShape &b, SpinorFmt fx, SpinorFmt fp, SpinorFmt fr,
+                        SpinorFmt fap, void *x, const void *p, void *r, const void *ap,
+                        const double *rho, const double *pi, const double *pi2,
+                        const int *active, const Reduce &red, hipStream_t st) {
+    // supported combinations: all equal, or (x FP32, p FP16, r FP32, Ap FP16)
+    if (fx == fp && fp == fr && fr == fap) {
+        DISPATCH_FMT(fx, F,
+                     XrFn<F, F, F, F> fn{x, p, r, ap, block_bytes(F, b.S, b.R), block_bytes(F, b.S, b.R),
+                                         block_bytes(F, b.S, b.R), block_bytes(F, b.S, b.R),
+                                         rho, pi, pi2, active, b.S, b.R};
+                     return run(fn, b, &red, st));
+    }
+    if (fx == SpinorFmt::F32 && fp == SpinorFmt::F16 && fr == SpinorFmt::F32 &&
+        fap == SpinorFmt::F16) {
+        XrFn<SpinorFmt::F32, SpinorFmt::F16, SpinorFmt::F32, SpinorFmt::F16> fn{
+            x, p, r, ap,
+            block_bytes(SpinorFmt::F32, b.S, b.R), block_bytes(SpinorFmt::F16, b.S, b.R),
+            block_bytes(SpinorFmt::F32, b.S, b.R), block_bytes(SpinorFmt::F16, b.S, b.R),
+            rho, pi, pi2, active, b.S, b.R};
+        return run(fn, b, &red, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_cg_p(const BlasShape &b, SpinorFmt fr, SpinorFmt fp, const void *r, void *p,
+                       const double *rho_new, const double *rho, const int *active,
+                       hipStream_t st) {
+    if (fr == fp) {
+        DISPATCH_FMT(fr, F,
+                     PFn<F, F> fn{r, p, block_bytes(F, b.S, b.R), block_bytes(F, b.S, b.R),
+                                  rho_new, rho, active, b.S, b.R};
+                     return run(fn, b, nullptr, st));
+    }
+    if (fr == SpinorFmt::F32 && fp == SpinorFmt::F16) {
+        PFn<SpinorFmt::F32, SpinorFmt::F16> fn{r, p, block_bytes(fr, b.S, b.R),
+                                               block_bytes(fp, b.S, b.R), rho_new, rho, active,
+                                               b.S, b.R};
+        return run(fn, b, nullptr, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_norm2(const BlasShape &b, SpinorFmt f, const void *v, const Reduce &red,
+                        hipStream_t st) {
+    DISPATCH_FMT(f, F, NormFn<F> fn{v, block_bytes(F, b.S, b.R), b.S, b.R};
+                 return run(fn, b, &red, st));
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_convert(const BlasShape &b, SpinorFmt fd, SpinorFmt fs, void *dst,
+                          const void *src, const double *s, int inv_scale, const Reduce *red,
+                          hipStream_t st) {
+    DISPATCH_FMT(fd, FD, DISPATCH_FMT(fs, FS,
+                 ConvFn<FD, FS> fn{dst, src, block_bytes(FD, b.S, b.R), block_bytes(FS, b.S, b.R),
+                                   s, inv_scale, b.S, b.R};
+                 return run(fn, b, red, st)));
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_accum(const BlasShape &b, SpinorFmt fs, void *dst, void *src, const double *s,
+                        int zero_src, hipStream_t st) {
+    DISPATCH_FMT(fs, FS,
+                 AccumFn<FS> fn{dst, src, block_bytes(SpinorFmt::F64, b.S, b.R),
+                                block_bytes(FS, b.S, b.R), s, zero_src, b.S, b.R};
+                 return run(fn, b, nullptr, st));
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_residual(const BlasShape &b, void *r, const void *bb, const void *ax,
+                           const Reduce &red, hipStream_t st) {
+    ResidualFn fn{r, bb, ax, block_bytes(SpinorFmt::F64, b.S, b.R), b.S, b.R};
+    return run(fn, b, &red, st);
+}
+
+hipError_t launch_clover_site(const BlasShape &b, SpinorFmt f, int clov_double, void *out,
+                              const void *in, const void *clov, int parity, hipStream_t st) {
+    if (clov_double) {
+        DISPATCH_FMT(f, F, CloverFn<F, double> fn{out, in, clov, block_bytes(F, b.S, b.R),
+                                                  parity, b.S, b.R};
+                     return run(fn, b, nullptr, st));
+    } else {
+        DISPATCH_FMT(f, F, CloverFn<F, float> fn{out, in, clov, block_bytes(F, b.S, b.R),
+                                                 parity, b.S, b.R};
+                     return run(fn, b, nullptr, st));
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace cola

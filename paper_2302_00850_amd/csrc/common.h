@@ -1,0 +1,100 @@
+// Internal definitions shared by the HIP kernels and the host library.
+//
+// Packed (library-internal) layouts, all per parity p (0 even, 1 odd):
+//   checkerboard index i of a site of parity p: i = (x + Lx*(y + Ly*(z + Lz*t))) / 2,
+//   0 <= i < Vh = V/2; arrays are padded to a stride S = Vh rounded up to 64.
+//   spinor block (one parity, R right-hand sides): complex element of spin-colour
+//     component c (= 3*spin + colour), site i, rhs r at ((c*S + i)*R + r); for FP16
+//     the block continues with one float scale per (i, r) at index i*R + r.
+//     A full-lattice field is the even block followed by the odd block.
+//   gauge (one precision): chunk k of link U_mu at site i of parity p at
+//     ((p*4 + mu)*NCH + k)*S + i, NCH chunks of 16 bytes (8 for FP16).
+//   clover (one precision): real pair k (0..35) of site i, parity p at (p*36 + k)*S + i;
+//     two Hermitian 6x6 chiral blocks, each 6 diagonal reals then the 15 complex
+//     entries below the diagonal, row-major.
+#pragma once
+
+#include <stdint.h>
+
+namespace cola {
+
+constexpr int kStrideAlign = 64;
+
+// Division by a runtime-constant divisor with a multiply-high and a shift
+// (Granlund & Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994).  Exact for numerators below 2^31.
+struct FastDiv {
+    uint32_t d, m, s;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f;
+    f.d = d;
+    uint32_t s = 0;
+    while ((1ull << s) < d) ++s;
+    f.s = s;
+    f.m = (uint32_t)((((1ull << 32) * ((1ull << s) - d)) / d) + 1);
+    return f;
+}
+
+struct Geom {
+    int L[4];        // Lx, Ly, Lz, Lt
+    int Lxh;         // Lx / 2
+    int Vh;          // sites of one parity
+    int S;           // padded per-parity stride
+    int s1, s2, s3;  // checkerboard strides of y, z, t: Lxh, Lxh*Ly, Lxh*Ly*Lz
+    FastDiv div_xh, div_y, div_z;
+};
+
+enum class SpinorFmt : int { F64 = 0, F32 = 1, F16 = 2 };
+enum class LinkFmt : int { F64_18 = 0, F64_12 = 1, F32_12 = 2, F16_12 = 3 };
+
+enum Epilogue : int {
+    EPI_NONE = 0,        // out = D in
+    EPI_XPAY = 1,        // out = x + a D in
+    EPI_CLOV = 2,        // out = C (D in)              C: clover blocks of the output parity
+    EPI_CLOV_XPAY = 3,   // out = C x + a D in
+    EPI_XPAY_CLOV = 4    // out = C (x + a D in)
+};
+
+struct Cplx64 {
+    double x, y;
+};
+
+struct HopArgs {
+    Geom g;
+    int parity;      // output parity
+    int dagger;      // 0: D, 1: D^H
+    int nrhs;        // R
+    int groups;      // R / rhs-per-thread
+    FastDiv div_groups;
+    int epi;         // Epilogue
+    int want_norm;   // accumulate |out|^2 per rhs into `result`
+    double a;        // epilogue coefficient
+    Cplx64 phase[4]; // boundary phases e^{i theta_mu}
+    const void *in;      // parity (1 - parity) block
+    void *out;           // parity `parity` block
+    const void *x;       // parity `parity` block (epilogues 1, 3, 4)
+    const void *gauge;   // packed gauge buffer of the launch precision
+    const void *clov;    // packed clover buffer (both parities) for epilogues 2-4
+    double *partial;     // per-block partial sums [grid][R]
+    unsigned *counter;   // last-block ticket, left at 0
+    double *result;      // [R]
+    uint32_t total;      // Vh * groups threads of work
+    int sites_per_block; // T: threads per block = T * groups
+};
+
+// Link chunk counts per format.
+constexpr int link_chunks(LinkFmt f) {
+    return f == LinkFmt::F64_18 ? 9 : f == LinkFmt::F64_12 ? 6 : 3;
+}
+constexpr int link_chunk_bytes(LinkFmt f) { return f == LinkFmt::F16_12 ? 8 : 16; }
+constexpr int link_reals(LinkFmt f) { return f == LinkFmt::F64_18 ? 18 : 12; }
+constexpr int link_real_bytes(LinkFmt f) {
+    return f == LinkFmt::F16_12 ? 2 : f == LinkFmt::F32_12 ? 4 : 8;
+}
+constexpr int spinor_real_bytes(SpinorFmt f) {
+    return f == SpinorFmt::F64 ? 8 : f == SpinorFmt::F32 ? 4 : 2;
+}
+
+}  // namespace cola

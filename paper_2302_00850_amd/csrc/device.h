@@ -1,0 +1,424 @@
+// Device-side building blocks: complex arithmetic, site geometry, packed
+// spinor/link/clover access and the deterministic block reduction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace cola {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) {
+    return {a.x + b.x, a.y + b.y};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) {
+    return {a.x - b.x, a.y - b.y};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> scale(T s, cpx<T> a) {
+    return {s * a.x, s * a.y};
+}
+// a * b
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// acc + a * b
+template <typename T>
+__device__ __forceinline__ cpx<T> cmadd(cpx<T> acc, cpx<T> a, cpx<T> b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+// acc + conj(a) * b
+template <typename T>
+__device__ __forceinline__ cpx<T> cjmadd(cpx<T> acc, cpx<T> a, cpx<T> b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+// a + s*i*b for a real sign s
+template <typename T>
+__device__ __forceinline__ cpx<T> add_si(cpx<T> a, T s, cpx<T> b) {
+    return {fma(-s, b.y, a.x), fma(s, b.x, a.y)};
+}
+// a + s*b
+template <typename T>
+__device__ __forceinline__ cpx<T> add_s(cpx<T> a, T s, cpx<T> b) {
+    return {fma(s, b.x, a.x), fma(s, b.y, a.y)};
+}
+template <typename T>
+__device__ __forceinline__ T norm2(cpx<T> a) {
+    return a.x * a.x + a.y * a.y;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
+    return (__umulhi(n, f.m) + n) >> f.s;
+}
+
+// Coordinates of checkerboard site i of parity p.
+__device__ __forceinline__ void site_coords(const Geom &g, uint32_t i, int p, int x[4]) {
+    const uint32_t r0 = fdiv(i, g.div_xh);
+    const uint32_t xh = i - r0 * (uint32_t)g.Lxh;
+    const uint32_t r1 = fdiv(r0, g.div_y);
+    x[1] = (int)(r0 - r1 * (uint32_t)g.L[1]);
+    const uint32_t r2 = fdiv(r1, g.div_z);
+    x[2] = (int)(r1 - r2 * (uint32_t)g.L[2]);
+    x[3] = (int)r2;
+    x[0] = 2 * (int)xh + ((x[1] + x[2] + x[3] + p) & 1);
+}
+
+// Checkerboard index of the neighbour x +- mu (opposite parity).
+__device__ __forceinline__ uint32_t nb_fwd(const Geom &g, uint32_t i, const int x[4], int mu) {
+    switch (mu) {
+        case 0: {
+            const uint32_t base = i - (uint32_t)(x[0] >> 1);
+            const int xf = x[0] + 1 == g.L[0] ? 0 : x[0] + 1;
+            return base + (uint32_t)(xf >> 1);
+        }
+        case 1: return x[1] == g.L[1] - 1 ? i - (uint32_t)((g.L[1] - 1) * g.s1) : i + g.s1;
+        case 2: return x[2] == g.L[2] - 1 ? i - (uint32_t)((g.L[2] - 1) * g.s2) : i + g.s2;
+        default: return x[3] == g.L[3] - 1 ? i - (uint32_t)((g.L[3] - 1) * g.s3) : i + g.s3;
+    }
+}
+__device__ __forceinline__ uint32_t nb_bwd(const Geom &g, uint32_t i, const int x[4], int mu) {
+    switch (mu) {
+        case 0: {
+            const uint32_t base = i - (uint32_t)(x[0] >> 1);
+            const int xb = x[0] == 0 ? g.L[0] - 1 : x[0] - 1;
+            return base + (uint32_t)(xb >> 1);
+        }
+        case 1: return x[1] == 0 ? i + (uint32_t)((g.L[1] - 1) * g.s1) : i - g.s1;
+        case 2: return x[2] == 0 ? i + (uint32_t)((g.L[2] - 1) * g.s2) : i - g.s2;
+        default: return x[3] == 0 ? i + (uint32_t)((g.L[3] - 1) * g.s3) : i - g.s3;
+    }
+}
+
+// ------------------------------------------------------------------ spinors
+
+struct alignas(4) half2s {
+    _Float16 x, y;
+};
+
+template <SpinorFmt F>
+struct SpinorT;
+template <>
+struct SpinorT<SpinorFmt::F64> {
+    using real = double;
+    using elem = cpx<double>;
+};
+template <>
+struct SpinorT<SpinorFmt::F32> {
+    using real = float;
+    using elem = cpx<float>;
+};
+template <>
+struct SpinorT<SpinorFmt::F16> {
+    using real = float;
+    using elem = half2s;
+};
+
+// View of one parity block of a packed spinor field.
+template <SpinorFmt F>
+struct SpinorBlock {
+    using E = typename SpinorT<F>::elem;
+    using R = typename SpinorT<F>::real;
+    E *data;
+    float *norm;     // FP16 only
+    uint32_t SR;     // S * nrhs: distance between components
+    uint32_t nrhs;
+
+    __device__ __forceinline__ SpinorBlock(const void *base, int S, int nr)
+        : data((E *)base), norm(nullptr), SR((uint32_t)S * nr), nrhs(nr) {
+        if (F == SpinorFmt::F16) norm = (float *)(data + 12 * (size_t)SR);
+    }
+
+    // the 12 components of site i, rhs r, in compute precision
+    __device__ __forceinline__ void load(uint32_t i, uint32_t r, cpx<R> v[12]) const {
+        const uint32_t e = i * nrhs + r;
+        if constexpr (F == SpinorFmt::F16) {
+            const float s = norm[e];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const half2s h = data[c * SR + e];
+                v[c] = {s * (float)h.x, s * (float)h.y};
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const E h = data[c * SR + e];
+                v[c] = {h.x, h.y};
+            }
+        }
+    }
+
+    // Store; v is replaced by the values actually stored (FP16 rounding).
+    __device__ __forceinline__ void store(uint32_t i, uint32_t r, cpx<R> v[12]) const {
+        const uint32_t e = i * nrhs + r;
+        if constexpr (F == SpinorFmt::F16) {
+            float m = 0.f;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].x), fabsf(v[c].y)));
+            const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                half2s h;
+                h.x = (_Float16)(v[c].x * inv);
+                h.y = (_Float16)(v[c].y * inv);
+                data[c * SR + e] = h;
+                v[c] = {m * (float)h.x, m * (float)h.y};
+            }
+            norm[e] = m;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) data[c * SR + e] = E{v[c].x, v[c].y};
+        }
+    }
+};
+
+// ------------------------------------------------------------------- links
+
+template <LinkFmt F>
+struct LinkT;
+template <>
+struct LinkT<LinkFmt::F64_18> {
+    using real = double;
+    struct alignas(16) chunk { double a, b; };
+};
+template <>
+struct LinkT<LinkFmt::F64_12> {
+    using real = double;
+    struct alignas(16) chunk { double a, b; };
+};
+template <>
+struct LinkT<LinkFmt::F32_12> {
+    using real = float;
+    struct alignas(16) chunk { float a, b, c, d; };
+};
+template <>
+struct LinkT<LinkFmt::F16_12> {
+    using real = float;
+    struct alignas(8) chunk { _Float16 a, b, c, d; };
+};
+
+// Load U_mu at checkerboard site i of parity p; row 2 rebuilt as conj(row0 x row1)
+// for the 12-real formats.
+template <LinkFmt F, typename T>
+__device__ __forceinline__ void load_link(const void *gauge, int S, int p, int mu, uint32_t i,
+                                          cpx<T> u[3][3]) {
+    using CH = typename LinkT<F>::chunk;
+    constexpr int N = link_chunks(F);
+    const CH *base = (const CH *)gauge + ((size_t)(p * 4 + mu) * N) * (size_t)S + i;
+    if constexpr (F == LinkFmt::F64_18) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const CH c = base[(size_t)k * S];
+            u[k / 3][k % 3] = {(T)c.a, (T)c.b};
+        }
+        return;
+    } else if constexpr (F == LinkFmt::F64_12) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const CH c = base[(size_t)k * S];
+            u[k / 3][k % 3] = {(T)c.a, (T)c.b};
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const CH c = base[(size_t)k * S];
+            u[(2 * k) / 3][(2 * k) % 3] = {(T)c.a, (T)c.b};
+            u[(2 * k + 1) / 3][(2 * k + 1) % 3] = {(T)c.c, (T)c.d};
+        }
+    }
+    if constexpr (F != LinkFmt::F64_18) {
+        // row 2 = conj(row 0 x row 1)
+        const cpx<T> *a = u[0], *b = u[1];
+        const cpx<T> c0 = cmul(a[1], b[2]) - cmul(a[2], b[1]);
+        const cpx<T> c1 = cmul(a[2], b[0]) - cmul(a[0], b[2]);
+        const cpx<T> c2 = cmul(a[0], b[1]) - cmul(a[1], b[0]);
+        u[2][0] = {c0.x, -c0.y};
+        u[2][1] = {c1.x, -c1.y};
+        u[2][2] = {c2.x, -c2.y};
+    }
+}
+
+// w = U h
+template <typename T>
+__device__ __forceinline__ void su3_mul(const cpx<T> u[3][3], const cpx<T> h[3], cpx<T> w[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cpx<T> s = cmul(u[a][0], h[0]);
+        s = cmadd(s, u[a][1], h[1]);
+        s = cmadd(s, u[a][2], h[2]);
+        w[a] = s;
+    }
+}
+// w = U^H h
+template <typename T>
+__device__ __forceinline__ void su3_dag_mul(const cpx<T> u[3][3], const cpx<T> h[3],
+                                            cpx<T> w[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cpx<T> s = {(T)0, (T)0};
+        s = cjmadd(s, u[0][a], h[0]);
+        s = cjmadd(s, u[1][a], h[1]);
+        s = cjmadd(s, u[2][a], h[2]);
+        w[a] = s;
+    }
+}
+
+// ------------------------------------------------------- spin projection
+
+// Spin projection with (1 + sg g_mu) in the chiral basis, sg = +-1:
+//   mu=x: h0 = p0 + sg i p3, h1 = p1 + sg i p2; lower: s2 += -sg i W1, s3 += -sg i W0
+//   mu=y: h0 = p0 - sg p3,   h1 = p1 + sg p2;   lower: s2 +=  sg W1,   s3 += -sg W0
+//   mu=z: h0 = p0 + sg i p2, h1 = p1 - sg i p3; lower: s2 += -sg i W0, s3 +=  sg i W1
+//   mu=t: h0 = p0 + sg p2,   h1 = p1 + sg p3;   lower: s2 +=  sg W0,   s3 +=  sg W1
+// where the upper spins receive W0 and W1.  expand_add(project(psi)) with W = h
+// is (1 + sg g_mu) psi.
+template <typename T>
+__device__ __forceinline__ void project(int mu, T sg, const cpx<T> p[12], cpx<T> h[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cpx<T> p0 = p[c], p1 = p[3 + c], p2 = p[6 + c], p3 = p[9 + c];
+        switch (mu) {
+            case 0: h[c] = add_si(p0, sg, p3); h[3 + c] = add_si(p1, sg, p2); break;
+            case 1: h[c] = add_s(p0, -sg, p3); h[3 + c] = add_s(p1, sg, p2); break;
+            case 2: h[c] = add_si(p0, sg, p2); h[3 + c] = add_si(p1, -sg, p3); break;
+            default: h[c] = add_s(p0, sg, p2); h[3 + c] = add_s(p1, sg, p3); break;
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void expand_add(int mu, T sg, const cpx<T> w[6], cpx<T> acc[12],
+                                           T s = (T)1) {
+    // acc += s * (1 + sg g_mu) expansion of (w0, w1); s is a real boundary phase
+    const T ts = sg * s;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cpx<T> w0 = w[c], w1 = w[3 + c];
+        acc[c] = add_s(acc[c], s, w0);
+        acc[3 + c] = add_s(acc[3 + c], s, w1);
+        switch (mu) {
+            case 0:
+                acc[6 + c] = add_si(acc[6 + c], -ts, w1);
+                acc[9 + c] = add_si(acc[9 + c], -ts, w0);
+                break;
+            case 1:
+                acc[6 + c] = add_s(acc[6 + c], ts, w1);
+                acc[9 + c] = add_s(acc[9 + c], -ts, w0);
+                break;
+            case 2:
+                acc[6 + c] = add_si(acc[6 + c], -ts, w0);
+                acc[9 + c] = add_si(acc[9 + c], ts, w1);
+                break;
+            default:
+                acc[6 + c] = add_s(acc[6 + c], ts, w0);
+                acc[9 + c] = add_s(acc[9 + c], ts, w1);
+                break;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ clover
+
+// out = C in, C = two Hermitian 6x6 chiral blocks (spins {0,1} and {2,3}).
+template <typename CR, typename T>
+__device__ __forceinline__ void clover_apply(const void *clov, int S, int p, uint32_t i,
+                                             const cpx<T> in[12], cpx<T> out[12]) {
+    struct pair { CR a, b; };
+    const pair *base = (const pair *)clov + (size_t)(p * 36) * S + i;
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+        const pair *q = base + (size_t)(blk * 18) * S;
+        T d[6];
+        cpx<T> o[15];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const pair v = q[(size_t)k * S];
+            d[2 * k] = (T)v.a;
+            d[2 * k + 1] = (T)v.b;
+        }
+#pragma unroll
+        for (int k = 0; k < 15; ++k) {
+            const pair v = q[(size_t)(3 + k) * S];
+            o[k] = {(T)v.a, (T)v.b};
+        }
+        const cpx<T> *v = in + 6 * blk;
+        cpx<T> *y = out + 6 * blk;
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            cpx<T> s = scale(d[r], v[r]);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                if (c < r) s = cmadd(s, o[r * (r - 1) / 2 + c], v[c]);
+                if (c > r) s = cjmadd(s, o[c * (c - 1) / 2 + r], v[c]);
+            }
+            y[r] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- reduction
+
+// Deterministic two-level sum of per-thread values.  The block's threads are
+// laid out as T "slots" (power of two) x `width` values; each thread passes
+// the values for columns q0 .. q0+n-1 of its slot.  Block sums go to
+// partial[blockIdx.x * width + q]; the last block to finish adds the partials
+// of all blocks in a fixed order into result[q] and re-arms the counter.
+// red must hold T * width doubles.
+template <int NV>
+__device__ void block_sum_to_result(double *red, int T, int width, int slot, int q0, int n,
+                                    const double (&v)[NV], double *partial, unsigned *counter,
+                                    double *result) {
+    const int tid = threadIdx.x;
+    const int nt = blockDim.x;
+    for (int k = tid; k < T * width; k += nt) red[k] = 0.0;
+    __syncthreads();
+    for (int k = 0; k < n; ++k) red[slot * width + q0 + k] = v[k];
+    __syncthreads();
+    for (int w = T >> 1; w > 0; w >>= 1) {
+        for (int k = tid; k < w * width; k += nt) red[k] += red[k + w * width];
+        __syncthreads();
+    }
+    for (int k = tid; k < width; k += nt) partial[(size_t)blockIdx.x * width + k] = red[k];
+    __shared__ unsigned ticket;
+    __threadfence();
+    __syncthreads();
+    if (tid == 0)
+        ticket = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (ticket != gridDim.x - 1) return;
+    __threadfence();
+    // last block: fixed-order sum over blocks, slot s handles blocks s, s+T, ...
+    const int nb = gridDim.x;
+    for (int k = tid; k < T * width; k += nt) {
+        const int s = k / width, q = k - s * width;
+        double acc = 0.0;
+        for (int b = s; b < nb; b += T)
+            acc += __hip_atomic_load(&partial[(size_t)b * width + q], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+        red[k] = acc;
+    }
+    __syncthreads();
+    for (int w = T >> 1; w > 0; w >>= 1) {
+        for (int k = tid; k < w * width; k += nt) red[k] += red[k + w * width];
+        __syncthreads();
+    }
+    for (int k = tid; k < width; k += nt) result[k] = red[k];
+    if (tid == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace cola

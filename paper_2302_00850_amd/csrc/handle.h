@@ -1,0 +1,126 @@
+// Library handle and host-side helpers shared by the C ABI, the operator
+// composition and the solvers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/cola.h"
+#include "common.h"
+#include "launch.h"
+
+namespace cola {
+
+constexpr int kMaxRhs = 16;
+constexpr int kMaxGrid = 65536;
+
+struct TuneEntry {
+    int rpt = 1;
+    int sites_per_block = 64;
+    int grid = 0;  // 0: one block per sites_per_block sites
+    double ms = 0;
+};
+
+// A pool of device vectors keyed by a small integer tag (kept until destroy).
+struct VecCache {
+    std::map<std::string, std::pair<void *, size_t>> bufs;
+};
+
+}  // namespace cola
+
+struct cola_handle {
+    int dims[4];
+    cola::Geom g;
+    double kappa = 0, csw = 0;
+    cola::Cplx64 phase[4];
+    unsigned flags = 0;
+    int device = 0;
+
+    // packed gauge fields by cola::LinkFmt
+    void *gauge[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool gauge_set = false;
+    bool su3 = false;
+    double su3_dev = 0;
+    // clover blocks (both parities): A and A^-1, FP64 and FP32
+    void *clov64 = nullptr, *clovinv64 = nullptr, *clov32 = nullptr, *clovinv32 = nullptr;
+
+    // reductions
+    double *partial = nullptr;  // kMaxGrid * kMaxRhs
+    unsigned *counter = nullptr;
+    double *scal = nullptr;  // scalar arrays, kScalSlots * kMaxRhs
+    int *active = nullptr;   // kMaxRhs
+    double *host_scal = nullptr;  // pinned mirror of scal
+    int *host_active = nullptr;   // pinned
+
+    cola::VecCache cache;
+    std::string err;
+
+    // timing of hop launches
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    std::vector<double> pending_bytes, pending_flops;
+    std::vector<int> pending_prec;
+    std::vector<hipEvent_t> event_pool;
+    cola_stats_t stats{};
+
+    // autotuning
+    int tune_mode = 0;
+    std::map<std::string, cola::TuneEntry> tune;
+};
+
+namespace cola {
+
+constexpr int kScalSlots = 16;
+
+int set_error(cola_handle_t *h, int code, const std::string &msg);
+int hip_error(cola_handle_t *h, hipError_t e, const char *what);
+
+#define COLA_HIP(h, call)                                      \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return ::cola::hip_error((h), e_, #call); \
+    } while (0)
+#define COLA_TRY(call)                \
+    do {                              \
+        int rc_ = (call);             \
+        if (rc_ < 0) return rc_;      \
+    } while (0)
+
+SpinorFmt spinor_fmt(int prec);
+LinkFmt link_fmt(int prec);
+size_t spinor_block_bytes(const Geom &g, SpinorFmt f, int nrhs);
+
+// device vector from the handle's cache (zero-filled on first allocation)
+int get_vec(cola_handle_t *h, const std::string &tag, size_t bytes, void **out);
+
+// the reduction target writing into scalar slot `slot`
+Reduce reduce_into(cola_handle_t *h, int slot);
+inline double *scal_slot(cola_handle_t *h, int slot) { return h->scal + slot * kMaxRhs; }
+
+// one half-lattice hop launch with epilogue
+struct HopCall {
+    void *out;
+    const void *in;
+    int parity;
+    int dagger;
+    int epi = EPI_NONE;
+    const void *x = nullptr;
+    double a = 0;
+    const void *clov = nullptr;
+    double *norm_result = nullptr;  // per-rhs |out|^2 (fused)
+};
+int hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, hipStream_t st);
+
+// composite operators on packed fields (see COLA_OP_*); norm_result (optional)
+// receives |out|^2 per rhs where the composition allows it to be fused.
+int apply_op(cola_handle_t *h, void *out, const void *in, int op, int parity, int prec, int nrhs,
+             hipStream_t st, double *norm_result = nullptr);
+
+// timing bookkeeping
+int flush_timing(cola_handle_t *h, bool wait_all);
+
+std::string tune_key(const cola_handle_t *h, int prec, int nrhs, int epi, int norm);
+
+}  // namespace cola

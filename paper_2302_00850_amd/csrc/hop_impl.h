@@ -1,0 +1,174 @@
+// Half-lattice Wilson hopping term for gfx950 (kernel template; each
+// precision is instantiated in its own translation unit).
+//
+// One lane owns one output site of parity p and RPT of its right-hand sides;
+// consecutive lanes take the right-hand-side groups of one site, then the
+// next site, so a site's link is fetched by neighbouring lanes of one
+// wavefront (one memory transaction) and reused from registers across the
+// lane's RPT right-hand sides.  Per direction: load the link (rows 0-1 for the
+// compressed formats, row 2 rebuilt in registers), load the neighbour spinor,
+// project it to two spin components with (1 -+ g_mu), multiply both colour
+// vectors by U or U^H, apply the boundary phase and expand back into the four
+// spin components.  Real boundary phases (theta = 0 or pi) fold into the
+// accumulation sign; complex ones are a complex multiply.  The epilogue is a
+// template parameter:
+//   EPI_NONE       out = D in
+//   EPI_XPAY       out = x + a D in
+//   EPI_CLOV       out = C (D in)
+//   EPI_CLOV_XPAY  out = C x + a D in
+//   EPI_XPAY_CLOV  out = C (x + a D in)
+// and |out|^2 per rhs can be accumulated with a deterministic block +
+// last-block sum.
+#pragma once
+
+#include "device.h"
+#include "launch.h"
+
+namespace cola {
+
+template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, int EPI, bool RPH>
+__global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
+    using T = typename SpinorT<SF>::real;
+    using C = cpx<T>;
+    extern __shared__ double red[];
+    const Geom &g = a.g;
+    const int p = a.parity;
+    const SpinorBlock<SF> in(a.in, g.S, a.nrhs);
+    const SpinorBlock<SF> out(a.out, g.S, a.nrhs);
+    const SpinorBlock<SF> xin(a.x ? a.x : a.out, g.S, a.nrhs);
+    const T sg_f = a.dagger ? (T)1 : (T)-1;
+    const T sg_b = -sg_f;
+    double nrm[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) nrm[r] = 0.0;
+
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < a.total; t += stride) {
+        const uint32_t i = fdiv(t, a.div_groups);
+        const uint32_t j = t - i * (uint32_t)a.groups;
+        int x[4];
+        site_coords(g, i, p, x);
+        C acc[RPT][12];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc[r][c] = {(T)0, (T)0};
+
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+            for (int dir = 0; dir < 2; ++dir) {
+                // dir 0: (1 + sg_f g_mu) e+ U_mu(x) psi(x+mu)
+                // dir 1: (1 + sg_b g_mu) e- U_mu(x-mu)^H psi(x-mu)
+                const uint32_t n = dir == 0 ? nb_fwd(g, i, x, mu) : nb_bwd(g, i, x, mu);
+                const T sg = dir == 0 ? sg_f : sg_b;
+                C u[3][3];
+                load_link<LF, T>(a.gauge, g.S, dir == 0 ? p : 1 - p, mu, dir == 0 ? i : n, u);
+                const bool bnd = dir == 0 ? x[mu] == g.L[mu] - 1 : x[mu] == 0;
+                T eta = (T)1;
+                C ph = {(T)1, (T)0};
+                if constexpr (RPH) {
+                    eta = bnd ? (T)a.phase[mu].x : (T)1;
+                } else {
+                    const T im = dir == 0 ? (T)a.phase[mu].y : -(T)a.phase[mu].y;
+                    ph = bnd ? C{(T)a.phase[mu].x, im} : C{(T)1, (T)0};
+                }
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    C s[12], h[6], w[6];
+                    in.load(n, j * RPT + r, s);
+                    project(mu, sg, s, h);
+                    if (dir == 0) {
+                        su3_mul(u, h, w);
+                        su3_mul(u, h + 3, w + 3);
+                    } else {
+                        su3_dag_mul(u, h, w);
+                        su3_dag_mul(u, h + 3, w + 3);
+                    }
+                    if constexpr (!RPH) {
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) w[k] = cmul(ph, w[k]);
+                    }
+                    expand_add(mu, sg, w, acc[r], eta);
+                }
+            }
+        }
+
+        const T ca = (T)a.a;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const uint32_t rr = j * RPT + r;
+            C o[12];
+            if constexpr (EPI == EPI_NONE) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) o[c] = acc[r][c];
+            } else if constexpr (EPI == EPI_XPAY) {
+                C xv[12];
+                xin.load(i, rr, xv);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) o[c] = add_s(xv[c], ca, acc[r][c]);
+            } else if constexpr (EPI == EPI_CLOV) {
+                clover_apply<CR, T>(a.clov, g.S, p, i, acc[r], o);
+            } else if constexpr (EPI == EPI_CLOV_XPAY) {
+                C xv[12], cx[12];
+                xin.load(i, rr, xv);
+                clover_apply<CR, T>(a.clov, g.S, p, i, xv, cx);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) o[c] = add_s(cx[c], ca, acc[r][c]);
+            } else {
+                C xv[12];
+                xin.load(i, rr, xv);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) xv[c] = add_s(xv[c], ca, acc[r][c]);
+                clover_apply<CR, T>(a.clov, g.S, p, i, xv, o);
+            }
+            out.store(i, rr, o);  // o now holds the stored (rounded) values
+            if (a.want_norm) {
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < 12; ++c) s += (double)norm2(o[c]);
+                nrm[r] += s;
+            }
+        }
+    }
+    if (a.want_norm) {
+        const int slot = threadIdx.x / a.groups;
+        const int jj = threadIdx.x - slot * a.groups;
+        block_sum_to_result<RPT>(red, a.sites_per_block, a.nrhs, slot, jj * RPT, RPT, nrm,
+                                 a.partial, a.counter, a.result);
+    }
+}
+
+template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, int EPI, bool RPH>
+hipError_t hop_launch_t(const HopArgs &a, int grid, int block, hipStream_t st) {
+    const size_t shm = a.want_norm ? (size_t)a.sites_per_block * a.nrhs * sizeof(double) : 0;
+    hipLaunchKernelGGL((hop_kernel<SF, LF, CR, RPT, EPI, RPH>), dim3(grid), dim3(block), shm, st,
+                       a);
+    return hipGetLastError();
+}
+
+template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, bool RPH>
+hipError_t hop_launch_epi(const HopArgs &a, int grid, int block, hipStream_t st) {
+    switch (a.epi) {
+        case EPI_NONE: return hop_launch_t<SF, LF, CR, RPT, EPI_NONE, RPH>(a, grid, block, st);
+        case EPI_XPAY: return hop_launch_t<SF, LF, CR, RPT, EPI_XPAY, RPH>(a, grid, block, st);
+        case EPI_CLOV: return hop_launch_t<SF, LF, CR, RPT, EPI_CLOV, RPH>(a, grid, block, st);
+        case EPI_CLOV_XPAY: return hop_launch_t<SF, LF, CR, RPT, EPI_CLOV_XPAY, RPH>(a, grid, block, st);
+        case EPI_XPAY_CLOV: return hop_launch_t<SF, LF, CR, RPT, EPI_XPAY_CLOV, RPH>(a, grid, block, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <SpinorFmt SF, LinkFmt LF, typename CR>
+hipError_t hop_launch_fmt(const HopArgs &a, int rpt, int grid, int block, hipStream_t st) {
+    bool real_phase = true;
+    for (int mu = 0; mu < 4; ++mu) real_phase &= a.phase[mu].y == 0.0;
+    if (real_phase) {
+        if (rpt == 1) return hop_launch_epi<SF, LF, CR, 1, true>(a, grid, block, st);
+    } else {
+        if (rpt == 1) return hop_launch_epi<SF, LF, CR, 1, false>(a, grid, block, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace cola

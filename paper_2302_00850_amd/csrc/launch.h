@@ -1,0 +1,80 @@
+// Host-callable launchers for the HIP kernels (all asynchronous on `st`).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace cola {
+
+// Reduction target: per-block partials, a last-block ticket (kept at 0 between
+// launches) and the per-rhs result array; T = site slots per block.
+struct Reduce {
+    double *partial;
+    unsigned *counter;
+    double *result;
+};
+
+// --- hop
+hipError_t launch_hop(const HopArgs &a, LinkFmt lf, int rpt, int grid, int block, hipStream_t st);
+
+// --- packing
+// canonical complex128 U -> every non-null packed format; maxdev receives the
+// largest SU(3) deviation (max |U U^H - 1|, |det U - 1|) as the bits of a double.
+hipError_t launch_pack_gauge(const Geom &g, const void *U, void *g64_18, void *g64_12,
+                             void *g32_12, void *g16_12, unsigned long long *maxdev,
+                             hipStream_t st);
+// canonical complex128 [nrhs][V][4][3] <-> packed; parity -1 = both parity blocks
+hipError_t launch_pack_spinor(const Geom &g, SpinorFmt f, void *dst, const void *src, int nrhs,
+                              int parity, hipStream_t st);
+hipError_t launch_unpack_spinor(const Geom &g, SpinorFmt f, void *dst, const void *src, int nrhs,
+                                int parity, hipStream_t st);
+
+// --- BLAS on packed blocks; nblk = 1 (one parity block) or 2 (full field)
+struct BlasShape {
+    int S, R, nblk;
+    int T;  // site slots per block; threads per block = T * R
+    int grid;
+};
+BlasShape blas_shape(const Geom &g, int nrhs, int nblk);
+
+// x += alpha p, r -= alpha Ap, result = |r|^2 ;
+// alpha_q = active_q ? rho_q / (pi_q + pi2_q) : 0   (pi2 may be null)
+hipError_t launch_cg_xr(const BlasShape &b, SpinorFmt fx, SpinorFmt fp, SpinorFmt fr,
+                        SpinorFmt fap, void *x, const void *p, void *r, const void *ap,
+                        const double *rho, const double *pi, const double *pi2,
+                        const int *active, const Reduce &red, hipStream_t st);
+// p = r + beta p ; beta_q = active_q ? rho_new_q / rho_q : 0
+hipError_t launch_cg_p(const BlasShape &b, SpinorFmt fr, SpinorFmt fp, const void *r, void *p,
+                       const double *rho_new, const double *rho, const int *active,
+                       hipStream_t st);
+// result = |v|^2 per rhs
+hipError_t launch_norm2(const BlasShape &b, SpinorFmt f, const void *v, const Reduce &red,
+                        hipStream_t st);
+// dst = s_q * src (s = NULL: 1; inv_scale: s_q -> 1/s_q), optional |dst|^2
+hipError_t launch_convert(const BlasShape &b, SpinorFmt fd, SpinorFmt fs, void *dst,
+                          const void *src, const double *s, int inv_scale, const Reduce *red,
+                          hipStream_t st);
+// dst(FP64) += s_q * src; zero_src: src = 0 afterwards
+hipError_t launch_accum(const BlasShape &b, SpinorFmt fs, void *dst, void *src, const double *s,
+                        int zero_src, hipStream_t st);
+// r = b - ax (all FP64), result = |r|^2
+hipError_t launch_residual(const BlasShape &b, void *r, const void *bb, const void *ax,
+                           const Reduce &red, hipStream_t st);
+// out = C in on the sites of parity `parity` (one block), C = clover blocks
+hipError_t launch_clover_site(const BlasShape &b, SpinorFmt f, int clov_double, void *out,
+                              const void *in, const void *clov, int parity, hipStream_t st);
+
+// --- clover
+// Builds A = 1 - kappa csw sum sigma F (two 6x6 chiral blocks) and A^-1 per site from
+// the canonical FP64 links; writes FP64 and FP32 packed copies.  bad counts sites
+// whose blocks were not positive definite.
+hipError_t launch_clover_build(const Geom &g, const void *U, double kappa, double csw,
+                               void *a64, void *ainv64, void *a32, void *ainv32, int *bad,
+                               hipStream_t st);
+
+// --- force
+hipError_t launch_force(const Geom &g, const void *gauge64_18, const void *X, const void *Y,
+                        void *F, double kappa, const Cplx64 phase[4], int mode, hipStream_t st);
+
+}  // namespace cola

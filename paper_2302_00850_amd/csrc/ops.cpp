@@ -1,0 +1,347 @@
+// Host side of the operators: hop launches (with launch-shape tuning and
+// optional event timing), composition of M, M^H, M^H M and the even-site
+// Schur complement from half-lattice hops, and small handle utilities.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "handle.h"
+
+namespace cola {
+
+int set_error(cola_handle_t *h, int code, const std::string &msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+int hip_error(cola_handle_t *h, hipError_t e, const char *what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return set_error(h, e == hipErrorOutOfMemory ? COLA_ENOMEM : COLA_EHIP, m);
+}
+
+SpinorFmt spinor_fmt(int prec) {
+    switch (prec) {
+        case COLA_FP64:
+        case COLA_FP64_12: return SpinorFmt::F64;
+        case COLA_FP32: return SpinorFmt::F32;
+        default: return SpinorFmt::F16;
+    }
+}
+
+LinkFmt link_fmt(int prec) {
+    switch (prec) {
+        case COLA_FP64: return LinkFmt::F64_18;
+        case COLA_FP64_12: return LinkFmt::F64_12;
+        case COLA_FP32: return LinkFmt::F32_12;
+        default: return LinkFmt::F16_12;
+    }
+}
+
+size_t spinor_block_bytes(const Geom &g, SpinorFmt f, int nrhs) {
+    const size_t SR = (size_t)g.S * nrhs;
+    switch (f) {
+        case SpinorFmt::F64: return 12 * SR * 16;
+        case SpinorFmt::F32: return 12 * SR * 8;
+        default: return 12 * SR * 4 + SR * 4;
+    }
+}
+
+int get_vec(cola_handle_t *h, const std::string &tag, size_t bytes, void **out) {
+    auto it = h->cache.bufs.find(tag);
+    if (it != h->cache.bufs.end() && it->second.second >= bytes) {
+        *out = it->second.first;
+        return COLA_OK;
+    }
+    if (it != h->cache.bufs.end()) {
+        COLA_HIP(h, hipDeviceSynchronize());
+        COLA_HIP(h, hipFree(it->second.first));
+        h->cache.bufs.erase(it);
+    }
+    void *p = nullptr;
+    COLA_HIP(h, hipMalloc(&p, bytes));
+    COLA_HIP(h, hipMemset(p, 0, bytes));
+    h->cache.bufs[tag] = {p, bytes};
+    *out = p;
+    return COLA_OK;
+}
+
+Reduce reduce_into(cola_handle_t *h, int slot) {
+    return Reduce{h->partial, h->counter, scal_slot(h, slot)};
+}
+
+std::string tune_key(const cola_handle_t *h, int prec, int nrhs, int epi, int norm) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "hop:%dx%dx%dx%d:p%d:r%d:e%d:n%d", h->dims[0], h->dims[1],
+             h->dims[2], h->dims[3], prec, nrhs, epi, norm);
+    return buf;
+}
+
+namespace {
+
+int spinor_site_bytes(SpinorFmt f) { return f == SpinorFmt::F64 ? 192 : f == SpinorFmt::F32 ? 96 : 52; }
+int link_bytes(LinkFmt f) { return link_chunks(f) * link_chunk_bytes(f); }
+
+void hop_work(const cola_handle_t *h, int prec, int nrhs, int epi, double *bytes, double *flops) {
+    const SpinorFmt sf = spinor_fmt(prec);
+    const LinkFmt lf = link_fmt(prec);
+    const double Vh = h->g.Vh;
+    double b = 8.0 * link_bytes(lf) + 2.0 * nrhs * spinor_site_bytes(sf);
+    double f = 1320.0 * nrhs + (lf == LinkFmt::F64_18 ? 0.0 : 8 * 42.0);
+    if (epi == EPI_XPAY || epi == EPI_CLOV_XPAY || epi == EPI_XPAY_CLOV) {
+        b += nrhs * spinor_site_bytes(sf);
+        f += 48.0 * nrhs;
+    }
+    if (epi == EPI_CLOV || epi == EPI_CLOV_XPAY || epi == EPI_XPAY_CLOV) {
+        b += 72.0 * (sf == SpinorFmt::F64 ? 8 : 4);
+        f += 552.0 * nrhs;
+    }
+    *bytes = b * Vh;
+    *flops = f * Vh;
+}
+
+hipEvent_t take_event(cola_handle_t *h) {
+    if (!h->event_pool.empty()) {
+        hipEvent_t e = h->event_pool.back();
+        h->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch shape for one hop launch.
+void shape_for(const TuneEntry &t, int Vh, int nrhs, int *groups, int *T, int *grid, int *block) {
+    *groups = nrhs / t.rpt;
+    *T = t.sites_per_block;
+    *block = *T * *groups;
+    long g = (Vh + *T - 1) / *T;
+    if (t.grid > 0 && t.grid < g) g = t.grid;
+    if (g > kMaxGrid) g = kMaxGrid;
+    *grid = (int)std::max(1L, g);
+}
+
+TuneEntry default_entry(int nrhs) {
+    TuneEntry t;
+    t.rpt = 1;
+    const int G = nrhs;
+    int T = 1;
+    while (T * 2 * G <= 256) T *= 2;
+    t.sites_per_block = T;
+    t.grid = 0;
+    return t;
+}
+
+int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, const TuneEntry &te,
+                    hipStream_t st) {
+    HopArgs a;
+    memset(&a, 0, sizeof a);
+    a.g = h->g;
+    a.parity = c.parity;
+    a.dagger = c.dagger;
+    a.nrhs = nrhs;
+    int groups, T, grid, block;
+    shape_for(te, h->g.Vh, nrhs, &groups, &T, &grid, &block);
+    a.groups = groups;
+    a.div_groups = make_fastdiv((uint32_t)groups);
+    a.epi = c.epi;
+    a.want_norm = c.norm_result != nullptr;
+    a.a = c.a;
+    for (int mu = 0; mu < 4; ++mu) a.phase[mu] = h->phase[mu];
+    a.in = c.in;
+    a.out = c.out;
+    a.x = c.x;
+    a.gauge = h->gauge[(int)link_fmt(prec)];
+    a.clov = c.clov;
+    a.partial = h->partial;
+    a.counter = h->counter;
+    a.result = c.norm_result;
+    a.total = (uint32_t)h->g.Vh * (uint32_t)groups;
+    a.sites_per_block = T;
+    COLA_HIP(h, launch_hop(a, link_fmt(prec), te.rpt, grid, block, st));
+    return COLA_OK;
+}
+
+int tune_hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, TuneEntry *best,
+             hipStream_t st) {
+    std::vector<TuneEntry> cand;
+    for (int rpt : {1}) {
+        if (nrhs % rpt) continue;
+        const int G = nrhs / rpt;
+        for (int T : {4, 8, 16, 32, 64, 128, 256}) {
+            if (T * G > 256 || T * G < 64) continue;
+            for (int grid : {0, 2048, 8192}) {
+                TuneEntry t;
+                t.rpt = rpt;
+                t.sites_per_block = T;
+                t.grid = grid;
+                cand.push_back(t);
+            }
+        }
+    }
+    hipEvent_t e0, e1;
+    COLA_HIP(h, hipEventCreate(&e0));
+    COLA_HIP(h, hipEventCreate(&e1));
+    double best_ms = 1e30;
+    for (auto &t : cand) {
+        COLA_TRY(fill_and_launch(h, c, prec, nrhs, t, st));  // warm-up
+        COLA_HIP(h, hipEventRecord(e0, st));
+        const int reps = 3;
+        for (int k = 0; k < reps; ++k) COLA_TRY(fill_and_launch(h, c, prec, nrhs, t, st));
+        COLA_HIP(h, hipEventRecord(e1, st));
+        COLA_HIP(h, hipEventSynchronize(e1));
+        float ms = 0;
+        COLA_HIP(h, hipEventElapsedTime(&ms, e0, e1));
+        t.ms = ms / reps;
+        if (t.ms < best_ms) {
+            best_ms = t.ms;
+            *best = t;
+        }
+    }
+    COLA_HIP(h, hipEventDestroy(e0));
+    COLA_HIP(h, hipEventDestroy(e1));
+    return COLA_OK;
+}
+
+}  // namespace
+
+int flush_timing(cola_handle_t *h, bool wait_all) {
+    size_t done = 0;
+    for (; done < h->pending.size(); ++done) {
+        auto &pr = h->pending[done];
+        if (wait_all) {
+            COLA_HIP(h, hipEventSynchronize(pr.second));
+        } else if (hipEventQuery(pr.second) != hipSuccess) {
+            break;
+        }
+        float ms = 0;
+        COLA_HIP(h, hipEventElapsedTime(&ms, pr.first, pr.second));
+        const int pi = h->pending_prec[done];
+        h->stats.hop_launches[pi] += 1;
+        h->stats.hop_seconds[pi] += ms * 1e-3;
+        h->stats.hop_bytes[pi] += h->pending_bytes[done];
+        h->stats.hop_flops[pi] += h->pending_flops[done];
+        h->event_pool.push_back(pr.first);
+        h->event_pool.push_back(pr.second);
+    }
+    h->pending.erase(h->pending.begin(), h->pending.begin() + done);
+    h->pending_bytes.erase(h->pending_bytes.begin(), h->pending_bytes.begin() + done);
+    h->pending_flops.erase(h->pending_flops.begin(), h->pending_flops.begin() + done);
+    h->pending_prec.erase(h->pending_prec.begin(), h->pending_prec.begin() + done);
+    return COLA_OK;
+}
+
+int hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, hipStream_t st) {
+    if (!h->gauge_set) return set_error(h, COLA_ESTATE, "no gauge field set");
+    if (prec != COLA_FP64 && !h->su3)
+        return set_error(h, COLA_EINVAL,
+                         "compressed link formats need an SU(3) gauge field (check failed)");
+    if (!h->gauge[(int)link_fmt(prec)])
+        return set_error(h, COLA_EINVAL, "packed gauge field missing for this precision");
+    const std::string key = tune_key(h, prec, nrhs, c.epi, c.norm_result != nullptr);
+    TuneEntry te;
+    auto it = h->tune.find(key);
+    if (it != h->tune.end() && h->tune_mode != 2) {
+        te = it->second;
+    } else if (h->tune_mode >= 1) {
+        COLA_TRY(tune_hop(h, c, prec, nrhs, &te, st));
+        h->tune[key] = te;
+    } else {
+        te = default_entry(nrhs);
+    }
+    const bool timed = (h->flags & COLA_FLAG_TIMING) != 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        if (h->pending.size() > 2048) COLA_TRY(flush_timing(h, false));
+        if (h->pending.size() > 4096) COLA_TRY(flush_timing(h, true));
+        e0 = take_event(h);
+        e1 = take_event(h);
+        if (!e0 || !e1) return set_error(h, COLA_EHIP, "hipEventCreate failed");
+        COLA_HIP(h, hipEventRecord(e0, st));
+    }
+    COLA_TRY(fill_and_launch(h, c, prec, nrhs, te, st));
+    if (timed) {
+        COLA_HIP(h, hipEventRecord(e1, st));
+        double b, f;
+        hop_work(h, prec, nrhs, c.epi, &b, &f);
+        h->pending.push_back({e0, e1});
+        h->pending_bytes.push_back(b);
+        h->pending_flops.push_back(f);
+        h->pending_prec.push_back(prec);
+    }
+    return COLA_OK;
+}
+
+int apply_op(cola_handle_t *h, void *out, const void *in, int op, int parity, int prec, int nrhs,
+             hipStream_t st, double *norm_result) {
+    const SpinorFmt sf = spinor_fmt(prec);
+    const size_t bb = spinor_block_bytes(h->g, sf, nrhs);
+    const bool clover = h->csw != 0.0;
+    const bool f64 = sf == SpinorFmt::F64;
+    const void *A = f64 ? h->clov64 : h->clov32;
+    const void *Ainv = f64 ? h->clovinv64 : h->clovinv32;
+    const double k = h->kappa;
+    auto blk = [bb](const void *base, int p) { return (void *)((const char *)base + p * bb); };
+
+    switch (op) {
+        case COLA_OP_HOP:
+        case COLA_OP_HOP_DAG: {
+            HopCall c{out, in, parity, op == COLA_OP_HOP_DAG ? 1 : 0};
+            c.norm_result = norm_result;
+            return hop(h, c, prec, nrhs, st);
+        }
+        case COLA_OP_M:
+        case COLA_OP_MDAG: {
+            // out_p = A_pp in_p - kappa D_{p,1-p} in_{1-p}
+            const int dag = op == COLA_OP_MDAG;
+            for (int p = 0; p < 2; ++p) {
+                HopCall c{blk(out, p), blk(in, 1 - p), p, dag};
+                c.epi = clover ? EPI_CLOV_XPAY : EPI_XPAY;
+                c.x = blk(in, p);
+                c.a = -k;
+                c.clov = A;
+                COLA_TRY(hop(h, c, prec, nrhs, st));
+            }
+            return COLA_OK;
+        }
+        case COLA_OP_MDAGM: {
+            void *t;
+            COLA_TRY(get_vec(h, "op_full_" + std::to_string((int)sf) + "_" + std::to_string(nrhs),
+                             2 * bb, &t));
+            COLA_TRY(apply_op(h, t, in, COLA_OP_M, -1, prec, nrhs, st));
+            return apply_op(h, out, t, COLA_OP_MDAG, -1, prec, nrhs, st);
+        }
+        case COLA_OP_SCHUR:
+        case COLA_OP_SCHUR_DAG: {
+            // t_o = A_oo^-1 D_oe in_e ; out_e = A_ee in_e - kappa^2 D_eo t_o
+            const int dag = op == COLA_OP_SCHUR_DAG;
+            void *t;
+            COLA_TRY(get_vec(h, "op_odd_" + std::to_string((int)sf) + "_" + std::to_string(nrhs),
+                             bb, &t));
+            HopCall c1{t, in, 1, dag};
+            if (clover) {
+                c1.epi = EPI_CLOV;
+                c1.clov = Ainv;
+            }
+            COLA_TRY(hop(h, c1, prec, nrhs, st));
+            HopCall c2{out, t, 0, dag};
+            c2.epi = clover ? EPI_CLOV_XPAY : EPI_XPAY;
+            c2.x = in;
+            c2.a = -k * k;
+            c2.clov = A;
+            c2.norm_result = norm_result;
+            return hop(h, c2, prec, nrhs, st);
+        }
+        case COLA_OP_SCHUR_DAGSCHUR: {
+            void *t;
+            COLA_TRY(get_vec(h, "op_even_" + std::to_string((int)sf) + "_" + std::to_string(nrhs),
+                             bb, &t));
+            COLA_TRY(apply_op(h, t, in, COLA_OP_SCHUR, 0, prec, nrhs, st, norm_result));
+            return apply_op(h, out, t, COLA_OP_SCHUR_DAG, 0, prec, nrhs, st);
+        }
+        default: return set_error(h, COLA_EINVAL, "unknown operator");
+    }
+}
+
+}  // namespace cola

@@ -1,0 +1,460 @@
+// Conjugate-gradient solvers on the normal operator (M^H M on the full lattice
+// or S^H S on even sites), built from the hop and site kernels.
+//
+// All right-hand sides advance in lockstep (one batched hop per operator
+// factor).  Per-rhs scalars (rho, pi, alpha, beta) live on the device; the
+// host reads the residual norms back every `check_interval` iterations only.
+//
+// Schemes (the paper's benchmark is a mixed-precision solver with 32-bit
+// inner iterations and a 64-bit outer solver):
+//   FP64          plain CG; when the iterated residual meets tol the true
+//                 residual b - A x is recomputed and CG continues from it if
+//                 needed.
+//   FP32_RELIABLE FP32 CG (FP32 vectors, 12-real FP32 links) with an FP64
+//                 solution accumulator: every reliable_interval iterations
+//                 (and when the iterated residual meets tol) x64 += x32,
+//                 r = b - A64 x64 in FP64, and the FP32 residual is replaced;
+//                 the search direction is kept.
+//   FP16/FP32_DEFECT  FP64 defect correction: R = B - A64 X, inner CG on
+//                 A E = R/|R| in FP16 storage (FP32 arithmetic) or FP32 down
+//                 to inner_tol, X += |R| E.  Three cycles that contract the
+//                 residual by less than 2x switch an FP16 inner solve to FP32.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "handle.h"
+
+namespace cola {
+
+namespace {
+
+enum Slot { RHO = 0, RHO_NEW = 1, PI = 2, PI2 = 3, BNORM = 4, SCALE = 5, TRUE_RES = 6, TMP = 7 };
+
+struct Ctx {
+    cola_handle_t *h;
+    hipStream_t st;
+    int R;
+    int full;  // 1: M^H M on the full lattice (2 blocks), 0: S^H S on even sites
+    int nblk() const { return full ? 2 : 1; }
+    size_t bytes(SpinorFmt f) const { return spinor_block_bytes(h->g, f, R) * nblk(); }
+    BlasShape shape() const { return blas_shape(h->g, R, nblk()); }
+    double *slot(int s) const { return scal_slot(h, s); }
+};
+
+int vec(const Ctx &c, const char *tag, SpinorFmt f, void **out) {
+    std::string t = std::string("cg_") + tag + "_" + std::to_string((int)f) + "_" +
+                    std::to_string(c.R) + "_" + std::to_string(c.full);
+    return get_vec(c.h, t, c.bytes(f), out);
+}
+
+// out = A in, |first factor output|^2 -> PI (+PI2 on the full lattice)
+int normal(const Ctx &c, int prec, void *out, const void *in) {
+    if (!c.full)
+        return apply_op(c.h, out, in, COLA_OP_SCHUR_DAGSCHUR, 0, prec, c.R, c.st, c.slot(PI));
+    cola_handle_t *h = c.h;
+    const SpinorFmt sf = spinor_fmt(prec);
+    const size_t bb = spinor_block_bytes(h->g, sf, c.R);
+    void *t;
+    COLA_TRY(get_vec(h, "cg_full_t_" + std::to_string((int)sf) + "_" + std::to_string(c.R),
+                     2 * bb, &t));
+    const bool clover = h->csw != 0.0;
+    const void *A = sf == SpinorFmt::F64 ? h->clov64 : h->clov32;
+    for (int p = 0; p < 2; ++p) {
+        HopCall hc{(char *)t + p * bb, (const char *)in + (1 - p) * bb, p, 0};
+        hc.epi = clover ? EPI_CLOV_XPAY : EPI_XPAY;
+        hc.x = (const char *)in + p * bb;
+        hc.a = -h->kappa;
+        hc.clov = A;
+        hc.norm_result = c.slot(p == 0 ? PI : PI2);
+        COLA_TRY(hop(h, hc, prec, c.R, c.st));
+    }
+    return apply_op(h, out, t, COLA_OP_MDAG, -1, prec, c.R, c.st);
+}
+
+int zero_pi2(const Ctx &c) {
+    COLA_HIP(c.h, hipMemsetAsync(c.slot(PI2), 0, sizeof(double) * kMaxRhs, c.st));
+    return COLA_OK;
+}
+
+// r = b - A x in FP64 (x may be all zero); |r|^2 -> slot
+int true_residual(const Ctx &c, void *r, const void *b, const void *x, int slot) {
+    void *ax;
+    COLA_TRY(vec(c, "ax64", SpinorFmt::F64, &ax));
+    COLA_TRY(normal(c, COLA_FP64, ax, x));
+    const Reduce red = reduce_into(c.h, slot);
+    COLA_HIP(c.h, launch_residual(c.shape(), r, b, ax, red, c.st));
+    return COLA_OK;
+}
+
+int read_slot(const Ctx &c, int slot, double *out) {
+    COLA_HIP(c.h, hipMemcpyAsync(out, c.slot(slot), sizeof(double) * c.R, hipMemcpyDeviceToHost,
+                                 c.st));
+    COLA_HIP(c.h, hipStreamSynchronize(c.st));
+    return COLA_OK;
+}
+
+int write_active(const Ctx &c, const std::vector<int> &act) {
+    memcpy(c.h->host_active, act.data(), sizeof(int) * c.R);
+    COLA_HIP(c.h, hipMemcpyAsync(c.h->active, c.h->host_active, sizeof(int) * c.R,
+                                 hipMemcpyHostToDevice, c.st));
+    COLA_HIP(c.h, hipStreamSynchronize(c.st));  // the pinned staging area is reused
+    return COLA_OK;
+}
+
+int write_slot(const Ctx &c, int slot, const std::vector<double> &v) {
+    std::vector<double> tmp(v);
+    COLA_HIP(c.h, hipMemcpyAsync(c.slot(slot), tmp.data(), sizeof(double) * c.R,
+                                 hipMemcpyHostToDevice, c.st));
+    COLA_HIP(c.h, hipStreamSynchronize(c.st));
+    return COLA_OK;
+}
+
+bool finite_all(const double *v, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+// swap the RHO and RHO_NEW slots by copying (keeps slot numbering fixed)
+int rotate_rho(const Ctx &c) {
+    COLA_HIP(c.h, hipMemcpyAsync(c.slot(RHO), c.slot(RHO_NEW), sizeof(double) * c.R,
+                                 hipMemcpyDeviceToDevice, c.st));
+    return COLA_OK;
+}
+
+struct Outcome {
+    int status = COLA_OK;
+    int iterations = 0;
+    int outer = 0;
+    int reliable = 0;
+};
+
+// ---------------------------------------------------------------- FP64 / FP32 reliable
+
+int solve_reliable(const Ctx &c, int sloppy_prec, const cola_cg_params_t &p, void *x64,
+                   const void *b64, const std::vector<double> &thr, Outcome *o) {
+    cola_handle_t *h = c.h;
+    const BlasShape sh = c.shape();
+    const SpinorFmt fs = spinor_fmt(sloppy_prec);
+    const bool same = fs == SpinorFmt::F64;
+    const int check = p.check_interval > 0 ? p.check_interval : (same ? 8 : 10);
+    const int interval = same ? (1 << 30) : std::max(1, p.reliable_interval);
+    void *r64, *xs, *rs, *ps, *aps;
+    COLA_TRY(vec(c, "r64", SpinorFmt::F64, &r64));
+    COLA_TRY(vec(c, "ps", fs, &ps));
+    COLA_TRY(vec(c, "aps", fs, &aps));
+    if (same) {
+        xs = x64;
+        rs = r64;
+    } else {
+        COLA_TRY(vec(c, "xs", fs, &xs));
+        COLA_TRY(vec(c, "rs", fs, &rs));
+        COLA_HIP(h, hipMemsetAsync(xs, 0, c.bytes(fs), c.st));
+    }
+    // r = b - A x0, rho = |r|^2
+    COLA_TRY(true_residual(c, r64, b64, x64, TRUE_RES));
+    std::vector<double> rho(c.R), tr(c.R);
+    COLA_TRY(read_slot(c, TRUE_RES, tr.data()));
+    if (!finite_all(tr.data(), c.R)) {
+        o->status = COLA_BREAKDOWN;
+        return COLA_OK;
+    }
+    std::vector<int> act(c.R);
+    bool all_done = true;
+    for (int q = 0; q < c.R; ++q) {
+        act[q] = tr[q] > thr[q];
+        all_done &= !act[q];
+    }
+    if (all_done) return COLA_OK;
+    COLA_TRY(write_active(c, act));
+    const Reduce red_rho = reduce_into(h, RHO);
+    if (!same) COLA_HIP(h, launch_convert(sh, fs, SpinorFmt::F64, rs, r64, nullptr, 0, &red_rho, c.st));
+    else COLA_HIP(h, hipMemcpyAsync(c.slot(RHO), c.slot(TRUE_RES), sizeof(double) * c.R, hipMemcpyDeviceToDevice, c.st));
+    COLA_HIP(h, launch_convert(sh, fs, fs, ps, rs, nullptr, 0, nullptr, c.st));
+    if (!c.full) COLA_TRY(zero_pi2(c));
+    const Reduce red_new = reduce_into(h, RHO_NEW);
+    int last_rel = 0;
+    int it = 0;
+    while (it < p.max_iter) {
+        COLA_TRY(normal(c, sloppy_prec, aps, ps));
+        COLA_HIP(h, launch_cg_xr(sh, fs, fs, fs, fs, xs, ps, rs, aps, c.slot(RHO), c.slot(PI),
+                                 c.full ? c.slot(PI2) : nullptr, h->active, red_new, c.st));
+        ++it;
+        bool stop = false;
+        if (it % check == 0 || it == p.max_iter) {
+            COLA_TRY(read_slot(c, RHO_NEW, rho.data()));
+            if (!finite_all(rho.data(), c.R)) {
+                o->status = COLA_BREAKDOWN;
+                break;
+            }
+            bool iter_conv = true;
+            for (int q = 0; q < c.R; ++q) iter_conv &= !act[q] || rho[q] <= thr[q];
+            if (iter_conv || it - last_rel >= interval || it == p.max_iter) {
+                if (!same) {
+                    COLA_HIP(h, launch_accum(sh, fs, x64, xs, nullptr, 1, c.st));
+                }
+                COLA_TRY(true_residual(c, r64, b64, x64, TRUE_RES));
+                COLA_TRY(read_slot(c, TRUE_RES, tr.data()));
+                ++o->reliable;
+                last_rel = it;
+                bool done = true;
+                for (int q = 0; q < c.R; ++q) {
+                    act[q] = tr[q] > thr[q];
+                    done &= !act[q];
+                }
+                if (done) {
+                    stop = true;
+                } else {
+                    COLA_TRY(write_active(c, act));
+                    if (!same)
+                        COLA_HIP(h, launch_convert(sh, fs, SpinorFmt::F64, rs, r64, nullptr, 0,
+                                                   &red_new, c.st));
+                    else
+                        COLA_HIP(h, hipMemcpyAsync(c.slot(RHO_NEW), c.slot(TRUE_RES),
+                                                   sizeof(double) * c.R, hipMemcpyDeviceToDevice,
+                                                   c.st));
+                }
+            }
+        }
+        if (stop) break;
+        COLA_HIP(h, launch_cg_p(sh, fs, fs, rs, ps, c.slot(RHO_NEW), c.slot(RHO), h->active, c.st));
+        COLA_TRY(rotate_rho(c));
+    }
+    if (!same && o->status == COLA_OK) {
+        // fold any remaining sloppy solution in (no-op after a final reliable update)
+        COLA_HIP(h, launch_accum(sh, fs, x64, xs, nullptr, 1, c.st));
+    }
+    o->iterations += it;
+    if (o->status == COLA_OK && it >= p.max_iter) {
+        COLA_TRY(true_residual(c, r64, b64, x64, TRUE_RES));
+        COLA_TRY(read_slot(c, TRUE_RES, tr.data()));
+        for (int q = 0; q < c.R; ++q)
+            if (tr[q] > thr[q]) o->status = COLA_NOT_CONVERGED;
+    }
+    return COLA_OK;
+}
+
+// ---------------------------------------------------------------- defect correction
+
+int inner_cg(const Ctx &c, int prec, void *x, void *r, void *pv, void *ap, double inner_tol2,
+             int max_it, std::vector<int> act, int check, int *iters, int *status) {
+    cola_handle_t *h = c.h;
+    const BlasShape sh = c.shape();
+    const SpinorFmt fp = spinor_fmt(prec);
+    const SpinorFmt fx = SpinorFmt::F32;
+    const Reduce red_new = reduce_into(h, RHO_NEW);
+    COLA_TRY(write_active(c, act));
+    std::vector<double> rho(c.R);
+    int it = 0;
+    while (it < max_it) {
+        COLA_TRY(normal(c, prec, ap, pv));
+        COLA_HIP(h, launch_cg_xr(sh, fx, fp, fx, fp, x, pv, r, ap, c.slot(RHO), c.slot(PI),
+                                 c.full ? c.slot(PI2) : nullptr, h->active, red_new, c.st));
+        ++it;
+        if (it % check == 0) {
+            COLA_TRY(read_slot(c, RHO_NEW, rho.data()));
+            if (!finite_all(rho.data(), c.R)) {
+                *status = COLA_BREAKDOWN;
+                break;
+            }
+            bool any = false;
+            for (int q = 0; q < c.R; ++q) {
+                if (act[q] && rho[q] <= inner_tol2) act[q] = 0;
+                any |= act[q] != 0;
+            }
+            if (!any) break;
+            COLA_TRY(write_active(c, act));
+        }
+        COLA_HIP(h, launch_cg_p(sh, fx, fp, r, pv, c.slot(RHO_NEW), c.slot(RHO), h->active, c.st));
+        COLA_TRY(rotate_rho(c));
+    }
+    *iters = it;
+    return COLA_OK;
+}
+
+int solve_defect(const Ctx &c, int inner_prec, const cola_cg_params_t &p, void *x64,
+                 const void *b64, const std::vector<double> &thr, Outcome *o) {
+    cola_handle_t *h = c.h;
+    const BlasShape sh = c.shape();
+    const int check = p.check_interval > 0 ? p.check_interval : 8;
+    const double itol = p.inner_tol > 0 ? p.inner_tol : (inner_prec == COLA_FP16 ? 1e-2 : 1e-4);
+    void *r64, *x32, *r32;
+    COLA_TRY(vec(c, "r64", SpinorFmt::F64, &r64));
+    COLA_TRY(vec(c, "x32", SpinorFmt::F32, &x32));
+    COLA_TRY(vec(c, "r32", SpinorFmt::F32, &r32));
+    std::vector<double> tr(c.R), prev(c.R, -1.0), s(c.R);
+    int slow = 0;
+    int prec = inner_prec;
+    while (true) {
+        COLA_TRY(true_residual(c, r64, b64, x64, TRUE_RES));
+        COLA_TRY(read_slot(c, TRUE_RES, tr.data()));
+        if (!finite_all(tr.data(), c.R)) {
+            o->status = COLA_BREAKDOWN;
+            return COLA_OK;
+        }
+        std::vector<int> act(c.R);
+        bool done = true;
+        double worst = 0;
+        for (int q = 0; q < c.R; ++q) {
+            act[q] = tr[q] > thr[q];
+            done &= !act[q];
+            s[q] = std::sqrt(tr[q]);
+            if (act[q] && prev[q] > 0) worst = std::max(worst, std::sqrt(tr[q] / prev[q]));
+        }
+        if (done) return COLA_OK;
+        if (o->iterations >= p.max_iter) {
+            o->status = COLA_NOT_CONVERGED;
+            return COLA_OK;
+        }
+        if (o->outer > 0 && worst > 0.5) {
+            if (++slow >= 3 && prec == COLA_FP16) {
+                prec = COLA_FP32;
+                slow = 0;
+            }
+        } else {
+            slow = 0;
+        }
+        prev = tr;
+        COLA_TRY(write_slot(c, SCALE, s));
+        const SpinorFmt fp = spinor_fmt(prec);
+        void *pv, *ap;
+        COLA_TRY(vec(c, "dp", fp, &pv));
+        COLA_TRY(vec(c, "dap", fp, &ap));
+        const Reduce red_rho = reduce_into(h, RHO);
+        // r32 = R / |R|, rho = |r32|^2 ; p = r32 ; x32 = 0
+        COLA_HIP(h, launch_convert(sh, SpinorFmt::F32, SpinorFmt::F64, r32, r64, c.slot(SCALE), 1,
+                                   &red_rho, c.st));
+        COLA_HIP(h, launch_convert(sh, fp, SpinorFmt::F32, pv, r32, nullptr, 0, nullptr, c.st));
+        COLA_HIP(h, hipMemsetAsync(x32, 0, c.bytes(SpinorFmt::F32), c.st));
+        if (!c.full) COLA_TRY(zero_pi2(c));
+        int its = 0, st = COLA_OK;
+        COLA_TRY(inner_cg(c, prec, x32, r32, pv, ap, itol * itol, p.max_iter - o->iterations, act,
+                          check, &its, &st));
+        o->iterations += its;
+        ++o->outer;
+        if (st != COLA_OK) {
+            o->status = st;
+            return COLA_OK;
+        }
+        // X += |R| E
+        COLA_HIP(h, launch_accum(sh, SpinorFmt::F32, x64, x32, c.slot(SCALE), 0, c.st));
+    }
+}
+
+}  // namespace
+
+int cg_solve_impl(cola_handle_t *h, void *x, const void *b, int nrhs, const cola_cg_params_t *p,
+                  cola_cg_result_t *r, hipStream_t st) {
+    const auto t0 = std::chrono::steady_clock::now();
+    Ctx c{h, st, nrhs, p->system == COLA_SYS_MDAGM ? 1 : 0};
+    const BlasShape sh = c.shape();
+    const size_t bb64 = spinor_block_bytes(h->g, SpinorFmt::F64, nrhs);
+    void *b64, *x64, *bfull = nullptr;
+    COLA_TRY(vec(c, "b64", SpinorFmt::F64, &b64));
+    COLA_TRY(vec(c, "x64", SpinorFmt::F64, &x64));
+    const bool clover = h->csw != 0.0;
+
+    if (p->system == COLA_SYS_MDAGM) {
+        COLA_HIP(h, launch_pack_spinor(h->g, SpinorFmt::F64, b64, b, nrhs, -1, st));
+    } else if (p->system == COLA_SYS_SCHUR) {
+        COLA_HIP(h, launch_pack_spinor(h->g, SpinorFmt::F64, b64, b, nrhs, 0, st));
+    } else {
+        // b_hat_e = b_e + kappa D_eo A_oo^-1 b_o ; rhs = S^H b_hat_e
+        COLA_TRY(get_vec(h, "prop_b_full_" + std::to_string(nrhs), 2 * bb64, &bfull));
+        COLA_HIP(h, launch_pack_spinor(h->g, SpinorFmt::F64, bfull, b, nrhs, -1, st));
+        void *to, *bhat;
+        COLA_TRY(get_vec(h, "prop_to_" + std::to_string(nrhs), bb64, &to));
+        COLA_TRY(get_vec(h, "prop_bhat_" + std::to_string(nrhs), bb64, &bhat));
+        const void *bo = (const char *)bfull + bb64;
+        if (clover) {
+            COLA_HIP(h, launch_clover_site(blas_shape(h->g, nrhs, 1), SpinorFmt::F64, 1, to, bo,
+                                           h->clovinv64, 1, st));
+        } else {
+            COLA_HIP(h, hipMemcpyAsync(to, bo, bb64, hipMemcpyDeviceToDevice, st));
+        }
+        HopCall hc{bhat, to, 0, 0};
+        hc.epi = EPI_XPAY;
+        hc.x = bfull;
+        hc.a = h->kappa;
+        COLA_TRY(hop(h, hc, COLA_FP64, nrhs, st));
+        COLA_TRY(apply_op(h, b64, bhat, COLA_OP_SCHUR_DAG, 0, COLA_FP64, nrhs, st));
+    }
+    if (p->use_x0) {
+        COLA_HIP(h, hipMemsetAsync(x64, 0, c.bytes(SpinorFmt::F64), st));
+        COLA_HIP(h, launch_pack_spinor(h->g, SpinorFmt::F64, x64, x, nrhs, c.full ? -1 : 0, st));
+    } else {
+        COLA_HIP(h, hipMemsetAsync(x64, 0, c.bytes(SpinorFmt::F64), st));
+    }
+    // thresholds tol^2 |b_q|^2
+    std::vector<double> bn(nrhs), thr(nrhs);
+    const Reduce red_b = reduce_into(h, BNORM);
+    COLA_HIP(h, launch_norm2(sh, SpinorFmt::F64, b64, red_b, st));
+    COLA_TRY(read_slot(c, BNORM, bn.data()));
+    for (int q = 0; q < nrhs; ++q) thr[q] = p->tol * p->tol * bn[q];
+
+    Outcome o;
+    switch (p->scheme) {
+        case COLA_CG_FP64: COLA_TRY(solve_reliable(c, COLA_FP64, *p, x64, b64, thr, &o)); break;
+        case COLA_CG_FP32_RELIABLE:
+            COLA_TRY(solve_reliable(c, COLA_FP32, *p, x64, b64, thr, &o));
+            break;
+        case COLA_CG_FP16_DEFECT: COLA_TRY(solve_defect(c, COLA_FP16, *p, x64, b64, thr, &o)); break;
+        case COLA_CG_FP32_DEFECT: COLA_TRY(solve_defect(c, COLA_FP32, *p, x64, b64, thr, &o)); break;
+        default: return set_error(h, COLA_EINVAL, "unknown solver scheme");
+    }
+
+    // final FP64 true residual of the solved system
+    void *r64;
+    COLA_TRY(vec(c, "r64", SpinorFmt::F64, &r64));
+    COLA_TRY(true_residual(c, r64, b64, x64, TRUE_RES));
+    std::vector<double> tr(nrhs);
+    COLA_TRY(read_slot(c, TRUE_RES, tr.data()));
+    for (int q = 0; q < nrhs; ++q)
+        if (!(tr[q] <= thr[q]) && o.status == COLA_OK) o.status = COLA_NOT_CONVERGED;
+
+    if (p->system == COLA_SYS_PROPAGATOR) {
+        // x_o = A_oo^-1 (b_o + kappa D_oe x_e); residual of M x = b on the full lattice
+        void *xfull, *mx, *rf;
+        COLA_TRY(get_vec(h, "prop_x_full_" + std::to_string(nrhs), 2 * bb64, &xfull));
+        COLA_TRY(get_vec(h, "prop_mx_" + std::to_string(nrhs), 2 * bb64, &mx));
+        COLA_TRY(get_vec(h, "prop_r_" + std::to_string(nrhs), 2 * bb64, &rf));
+        COLA_HIP(h, hipMemcpyAsync(xfull, x64, bb64, hipMemcpyDeviceToDevice, st));
+        HopCall hc{(char *)xfull + bb64, x64, 1, 0};
+        hc.epi = clover ? EPI_XPAY_CLOV : EPI_XPAY;
+        hc.x = (const char *)bfull + bb64;
+        hc.a = h->kappa;
+        hc.clov = h->clovinv64;
+        COLA_TRY(hop(h, hc, COLA_FP64, nrhs, st));
+        COLA_TRY(apply_op(h, mx, xfull, COLA_OP_M, -1, COLA_FP64, nrhs, st));
+        const Reduce red_r = reduce_into(h, TRUE_RES), red_bf = reduce_into(h, BNORM);
+        const BlasShape shf = blas_shape(h->g, nrhs, 2);
+        COLA_HIP(h, launch_residual(shf, rf, bfull, mx, red_r, st));
+        COLA_HIP(h, launch_norm2(shf, SpinorFmt::F64, bfull, red_bf, st));
+        COLA_TRY(read_slot(c, TRUE_RES, tr.data()));
+        COLA_TRY(read_slot(c, BNORM, bn.data()));
+        COLA_HIP(h, launch_unpack_spinor(h->g, SpinorFmt::F64, x, xfull, nrhs, -1, st));
+    } else if (p->system == COLA_SYS_SCHUR) {
+        COLA_HIP(h, hipMemsetAsync(x, 0, (size_t)h->g.Vh * 2 * 12 * 16 * nrhs, st));
+        COLA_HIP(h, launch_unpack_spinor(h->g, SpinorFmt::F64, x, x64, nrhs, 0, st));
+    } else {
+        COLA_HIP(h, launch_unpack_spinor(h->g, SpinorFmt::F64, x, x64, nrhs, -1, st));
+    }
+    COLA_HIP(h, hipStreamSynchronize(st));
+    if (r) {
+        r->status = o.status;
+        r->iterations = o.iterations;
+        r->outer_cycles = o.outer;
+        r->reliable_updates = o.reliable;
+        if (r->true_rel_residual)
+            for (int q = 0; q < nrhs; ++q)
+                r->true_rel_residual[q] = bn[q] > 0 ? std::sqrt(tr[q] / bn[q]) : 0.0;
+        r->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return o.status;
+}
+
+}  // namespace cola

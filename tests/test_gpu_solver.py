@@ -1,0 +1,191 @@
+"""GPU CG solvers and fermion force against the FP64 oracle (through the C ABI).
+
+FP64 CG: both sides run exactly N iterations (N = the oracle's converged
+count) and the iterates agree to 1e-12 relative.  Mixed and multi-RHS
+schemes: the true residual of the GPU solution, recomputed by the oracle, is
+at most the requested tolerance.  Force: GPU kernel fed the oracle's X and Y
+agrees with the oracle force to 1e-12; the autograd path agrees to 1e-8.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2302_00850_amd.synth import Synth, bc_phases, point_sources
+from tests._util import rel
+
+pytestmark = pytest.mark.gpu
+
+cola = pytest.importorskip("paper_2302_00850_amd.cola")
+
+ANTI = bc_phases((0, 0, 0, np.pi))
+GENERIC = bc_phases((0.3, -0.5, 0.7, np.pi))
+DIMS = (6, 4, 4, 10)
+KAPPA = 0.12
+
+
+@pytest.fixture(scope="module")
+def fields():
+    s = Synth(202)
+    U = s.gauge(DIMS).numpy()
+    b = s.gaussian_spinor(DIMS, 12).numpy()
+    return U, b
+
+
+def _lat(U, bc, csw=0.0, kappa=KAPPA):
+    lat = cola.Lattice(tuple(U.shape[:4][::-1]), kappa, bc, csw)
+    lat.set_gauge(torch.from_numpy(U).cuda())
+    return lat
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _even(dims):
+    return oracle.parity_mask(dims)[..., None, None]
+
+
+def _normal_residual(U, x, b, system, kappa, bc, A=None, Ai=None):
+    if system == cola.COLA_SYS_MDAGM:
+        ax = oracle.apply_M(U, oracle.apply_M(U, x, kappa, bc, clover=A), kappa, bc, clover=A,
+                            dagger=True)
+        return rel(ax, b)
+    be = np.where(_even(DIMS), b, 0)
+    ax = oracle.apply_schur(U, oracle.apply_schur(U, x, kappa, bc, A, Ai), kappa, bc, A, Ai,
+                            dagger=True)
+    return rel(ax, be)
+
+
+@pytest.mark.parametrize("system", [cola.COLA_SYS_MDAGM, cola.COLA_SYS_SCHUR])
+def test_cg_fp64_fixed_iterations_match_oracle(fields, system):
+    U, b = fields
+    sysid = 0 if system == cola.COLA_SYS_MDAGM else 1
+    _, n, _ = oracle.cg(U, b[0], KAPPA, GENERIC, system=sysid, tol=1e-10)
+    assert n > 10
+    x_ref, _, _ = oracle.cg(U, b[0], KAPPA, GENERIC, system=sysid, fixed_iters=n)
+    lat = _lat(U, GENERIC)
+    x, info = lat.cg(_cuda(b[:1]), system=system, scheme=cola.COLA_CG_FP64, tol=1e-300,
+                     max_iter=n)
+    assert info["iterations"] == n and info["status"] == cola.COLA_NOT_CONVERGED
+    assert rel(x.cpu().numpy()[0], x_ref) <= 1e-12
+
+
+SCHEMES = [cola.COLA_CG_FP64, cola.COLA_CG_FP32_RELIABLE, cola.COLA_CG_FP16_DEFECT,
+           cola.COLA_CG_FP32_DEFECT]
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("system", [cola.COLA_SYS_MDAGM, cola.COLA_SYS_SCHUR])
+@pytest.mark.parametrize("nrhs", [1, 12])
+def test_cg_schemes_reach_tolerance(fields, scheme, system, nrhs):
+    U, b = fields
+    tol = 1e-10
+    src = b[:nrhs] if nrhs == 1 else point_sources(DIMS).numpy()
+    lat = _lat(U, ANTI)
+    x, info = lat.cg(_cuda(src), system=system, scheme=scheme, tol=tol)
+    assert info["status"] == cola.COLA_OK, info
+    xs = x.cpu().numpy()
+    for q in range(nrhs):
+        r = _normal_residual(U, xs[q], src[q], system, KAPPA, ANTI)
+        assert r <= 1.05 * tol, (scheme, system, q, r, info)
+        assert info["true_rel_residual"][q] <= tol
+    if system == cola.COLA_SYS_SCHUR:
+        assert np.all(np.where(_even(DIMS), 0, xs) == 0)
+
+
+@pytest.mark.parametrize("scheme", [cola.COLA_CG_FP64, cola.COLA_CG_FP32_DEFECT])
+def test_cg_clover_schur(fields, scheme):
+    U, b = fields
+    kappa, csw = 0.118, 1.0
+    A = oracle.clover(U, kappa, csw)
+    Ai = oracle.site_inverse(A)
+    lat = _lat(U, ANTI, csw=csw, kappa=kappa)
+    x, info = lat.cg(_cuda(b[:2]), system=cola.COLA_SYS_SCHUR, scheme=scheme, tol=1e-10)
+    assert info["status"] == cola.COLA_OK, info
+    xs = x.cpu().numpy()
+    for q in range(2):
+        assert _normal_residual(U, xs[q], b[q], cola.COLA_SYS_SCHUR, kappa, ANTI, A, Ai) <= 1.05e-10
+
+
+@pytest.mark.parametrize("csw", [0.0, 1.0])
+def test_propagator_solves_M(fields, csw):
+    U, b = fields
+    kappa = 0.118 if csw else KAPPA
+    A = oracle.clover(U, kappa, csw) if csw else None
+    lat = _lat(U, GENERIC, csw=csw, kappa=kappa)
+    x, info = lat.cg(_cuda(b[:1]), system=cola.COLA_SYS_PROPAGATOR, scheme=cola.COLA_CG_FP64,
+                     tol=1e-12)
+    assert info["status"] == cola.COLA_OK, info
+    xs = x.cpu().numpy()[0]
+    r = rel(oracle.apply_M(U, xs, kappa, GENERIC, clover=A), b[0])
+    assert r < 1e-9
+    assert r == pytest.approx(info["true_rel_residual"][0], rel=1e-3, abs=1e-14)
+
+
+def test_cg_not_converged_and_warm_start(fields):
+    U, b = fields
+    lat = _lat(U, ANTI)
+    x, info = lat.cg(_cuda(b[:1]), system=cola.COLA_SYS_SCHUR, tol=1e-10, max_iter=5)
+    assert info["status"] == cola.COLA_NOT_CONVERGED and info["iterations"] == 5
+    assert info["true_rel_residual"][0] > 1e-10
+    # resume from the partial solution
+    x2, info2 = lat.cg(_cuda(b[:1]), system=cola.COLA_SYS_SCHUR, tol=1e-10, x0=x)
+    assert info2["status"] == cola.COLA_OK
+    x3, info3 = lat.cg(_cuda(b[:1]), system=cola.COLA_SYS_SCHUR, tol=1e-10, x0=x2)
+    assert info3["iterations"] == 0 and info3["status"] == cola.COLA_OK
+
+
+def test_cg_breakdown_on_nan(fields):
+    U, b = fields
+    lat = _lat(U, ANTI)
+    bad = b[:1].copy()
+    bad[0, 0, 0, 0, 0, 0, 0] = np.nan
+    _, info = lat.cg(_cuda(bad), system=cola.COLA_SYS_MDAGM, tol=1e-10)
+    assert info["status"] == cola.COLA_BREAKDOWN
+
+
+def test_cg_duplicate_and_zero_columns(fields):
+    U, b = fields
+    lat = _lat(U, ANTI)
+    src = np.stack([b[0], b[0], np.zeros_like(b[0])])
+    x, info = lat.cg(_cuda(src), system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP16_DEFECT,
+                     tol=1e-10)
+    assert info["status"] == cola.COLA_OK
+    xs = x.cpu().numpy()
+    assert np.array_equal(xs[0], xs[1])
+    assert np.all(xs[2] == 0)
+
+
+# ------------------------------------------------------------------- force
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("bc", ["anti", "generic"])
+def test_force_kernel_matches_oracle(fields, mode, bc):
+    U, b = fields
+    bcv = ANTI if bc == "anti" else GENERIC
+    s = Synth(303)
+    X = s.gaussian_spinor(DIMS)[0].numpy()
+    Y = s.gaussian_spinor(DIMS)[0].numpy()
+    lat = _lat(U, bcv)
+    F = lat.force(_cuda(X), _cuda(Y), mode).cpu().numpy()
+    ref = oracle.force(U, X, Y, KAPPA, bcv, mode=mode)
+    assert rel(F, ref) <= 1e-13
+
+
+def test_pseudofermion_action_autograd(fields):
+    U, b = fields
+    s = Synth(404)
+    eta = s.gaussian_spinor(DIMS)[0].numpy()
+    phi = oracle.apply_M(U, eta, KAPPA, ANTI, dagger=True)
+    lat = _lat(U, ANTI)
+    Ut = torch.from_numpy(U).cuda().requires_grad_(True)
+    S = cola.PseudofermionAction.apply(Ut, _cuda(phi), lat, 1e-12)
+    S.backward()
+    X, _, _ = oracle.cg(U, phi, KAPPA, ANTI, system=0, tol=1e-13)
+    Y = oracle.apply_M(U, X, KAPPA, ANTI)
+    S_ref = np.vdot(phi, X).real
+    assert abs(S.item() - S_ref) <= 1e-10 * abs(S_ref)
+    assert abs(S.item() - np.vdot(eta, eta).real) <= 1e-9 * abs(S_ref)
+    G_ref = oracle.force(U, X, Y, KAPPA, ANTI, mode=0)
+    assert rel(Ut.grad.cpu().numpy(), G_ref) <= 1e-8
