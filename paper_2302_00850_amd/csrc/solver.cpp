@@ -141,8 +141,12 @@ int solve_reliable(const Ctx &c, int sloppy_prec, const cola_cg_params_t &p, voi
     const BlasShape sh = c.shape();
     const SpinorFmt fs = spinor_fmt(sloppy_prec);
     const bool same = fs == SpinorFmt::F64;
-    const int check = p.check_interval > 0 ? p.check_interval : (same ? 8 : 10);
+    const int check = p.check_interval > 0 ? p.check_interval : (same ? 8 : 5);
     const int interval = same ? (1 << 30) : std::max(1, p.reliable_interval);
+    // also update once the iterated residual has fallen by delta since the last
+    // update (Clark et al.): a sloppy residual far below the true one would make
+    // beta = rho_true / rho_iter huge and leave p pointing the stale way
+    const double delta2 = 1e-2;
     void *r64, *xs, *rs, *ps, *aps;
     COLA_TRY(vec(c, "r64", SpinorFmt::F64, &r64));
     COLA_TRY(vec(c, "ps", fs, &ps));
@@ -164,6 +168,7 @@ int solve_reliable(const Ctx &c, int sloppy_prec, const cola_cg_params_t &p, voi
         return COLA_OK;
     }
     std::vector<int> act(c.R);
+    std::vector<double> ref(tr);  // true |r|^2 at the last reliable update
     bool all_done = true;
     for (int q = 0; q < c.R; ++q) {
         act[q] = tr[q] > thr[q];
@@ -191,9 +196,12 @@ int solve_reliable(const Ctx &c, int sloppy_prec, const cola_cg_params_t &p, voi
                 o->status = COLA_BREAKDOWN;
                 break;
             }
-            bool iter_conv = true;
-            for (int q = 0; q < c.R; ++q) iter_conv &= !act[q] || rho[q] <= thr[q];
-            if (iter_conv || it - last_rel >= interval || it == p.max_iter) {
+            bool iter_conv = true, dropped = false;
+            for (int q = 0; q < c.R; ++q) {
+                iter_conv &= !act[q] || rho[q] <= thr[q];
+                dropped |= act[q] && rho[q] < delta2 * ref[q];
+            }
+            if (iter_conv || dropped || it - last_rel >= interval || it == p.max_iter) {
                 if (!same) {
                     COLA_HIP(h, launch_accum(sh, fs, x64, xs, nullptr, 1, c.st));
                 }
@@ -201,15 +209,19 @@ int solve_reliable(const Ctx &c, int sloppy_prec, const cola_cg_params_t &p, voi
                 COLA_TRY(read_slot(c, TRUE_RES, tr.data()));
                 ++o->reliable;
                 last_rel = it;
-                bool done = true;
+                bool done = true, restart = false;
+                std::vector<int> keep(c.R);
                 for (int q = 0; q < c.R; ++q) {
                     act[q] = tr[q] > thr[q];
                     done &= !act[q];
+                    ref[q] = tr[q];
+                    // true residual far above the iterated one: restart p = r
+                    keep[q] = act[q] && !(tr[q] > 1e4 * rho[q]);
+                    restart |= act[q] && !keep[q];
                 }
                 if (done) {
                     stop = true;
                 } else {
-                    COLA_TRY(write_active(c, act));
                     if (!same)
                         COLA_HIP(h, launch_convert(sh, fs, SpinorFmt::F64, rs, r64, nullptr, 0,
                                                    &red_new, c.st));
@@ -217,6 +229,16 @@ int solve_reliable(const Ctx &c, int sloppy_prec, const cola_cg_params_t &p, voi
                         COLA_HIP(h, hipMemcpyAsync(c.slot(RHO_NEW), c.slot(TRUE_RES),
                                                    sizeof(double) * c.R, hipMemcpyDeviceToDevice,
                                                    c.st));
+                    if (restart) {
+                        // beta = 0 for the restarted columns: p = r
+                        COLA_TRY(write_active(c, keep));
+                        COLA_HIP(h, launch_cg_p(sh, fs, fs, rs, ps, c.slot(RHO_NEW), c.slot(RHO),
+                                                h->active, c.st));
+                        COLA_TRY(rotate_rho(c));
+                        COLA_TRY(write_active(c, act));
+                        continue;
+                    }
+                    COLA_TRY(write_active(c, act));
                 }
             }
         }
