@@ -60,6 +60,66 @@ def cpu_baseline(U, b, budget_s=12.0):
                       f"(1536 B per output site)"}
 
 
+def hop_mode(args):
+    """Time the half-lattice hop alone: one JSON line per (precision, nrhs) case."""
+    import torch
+
+    from paper_2302_00850_amd import cola
+    from paper_2302_00850_amd.synth import Synth, bc_phases
+
+    dims = tuple(int(v) for v in args.lattice.split(","))
+    s = Synth(0, device="cuda")
+    U = s.gauge(dims)
+    bc = bc_phases((0, 0, 0, np.pi))
+    for prec in [int(p) for p in args.prec.split(",")]:
+        for nrhs in [int(r) for r in args.nrhs.split(",")]:
+            lat = cola.Lattice(dims, KAPPA, bc, 0.0, cola.COLA_FLAG_TIMING)
+            lat.set_gauge(U)
+            if args.tune:
+                cola.cola_set_tuning(lat.h, 1)
+            psi = s.gaussian_spinor(dims, nrhs)
+            pin = lat.pack(psi, prec, 1)
+            del psi
+            out = lat.empty_packed(prec, nrhs, 0)
+            for _ in range(3):
+                lat.dslash(out, pin, cola.COLA_OP_HOP, 0, prec, nrhs)
+            torch.cuda.synchronize()
+            lat.reset_stats()
+            t0 = time.perf_counter()
+            for _ in range(args.iters):
+                lat.dslash(out, pin, cola.COLA_OP_HOP, 0, prec, nrhs)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            st = lat.stats(prec)
+            rec = {"mode": "hop", "lattice": list(dims), "prec": prec, "nrhs": nrhs,
+                   "avg_ms": st["hop_seconds"] / st["hop_launches"] * 1e3,
+                   "wall_ms": wall / args.iters * 1e3,
+                   "GBs": st["hop_bytes"] / st["hop_seconds"] / 1e9,
+                   "GFLOPs": st["hop_flops"] / st["hop_seconds"] / 1e9,
+                   "bytes_per_site": st["hop_bytes"] / st["hop_launches"] / (np.prod(dims) / 2)}
+            rec["frac_hbm"] = rec["GBs"] / HBM_PEAK_GBS
+            if args.tune:
+                rec["tune"] = cola.cola_tune_dump(lat.h)
+            print(json.dumps(rec), flush=True)
+            lat.close()
+            del pin, out
+            torch.cuda.empty_cache()
+
+
+def copy_mode(args):
+    """A plain device-to-device copy of known size (HBM counter calibration)."""
+    import torch
+
+    n = 1 << 30
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.iters):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_read": n, "bytes_written": n,
+                      "copies": args.iters}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,11 +127,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
+    ap.add_argument("--mode", default="solve", choices=["solve", "hop", "copy"])
+    ap.add_argument("--lattice", default="32,32,32,64", help="hop mode: Lx,Ly,Lz,Lt")
+    ap.add_argument("--prec", default="0,2,3", help="hop mode: precisions (0 FP64 .. 3 FP16)")
+    ap.add_argument("--nrhs", default="1,12", help="hop mode: right-hand-side counts")
+    ap.add_argument("--iters", type=int, default=20, help="hop mode: timed launches")
+    ap.add_argument("--tune", action="store_true", help="hop mode: autotune launch shapes")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(domain decomposition is a design, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "hop":
+        hop_mode(args)
+        return
+    if args.mode == "copy":
+        copy_mode(args)
+        return
 
     import torch
 

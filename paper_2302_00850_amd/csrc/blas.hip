@@ -255,7 +255,7 @@ BlasShape blas_shape(const Geom &g, int nrhs, int nblk) {
     b.T = T;
     const size_t work = (size_t)g.S * nrhs * nblk;
     size_t grid = (work + (size_t)T * nrhs - 1) / ((size_t)T * nrhs);
-    if (grid > 8192) grid = 8192;
+    if (grid > 2048) grid = 2048;  // grid-stride; keeps the partial-sum array short
     b.grid = (int)(grid < 1 ? 1 : grid);
     return b;
 }

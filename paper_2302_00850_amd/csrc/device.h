@@ -403,14 +403,20 @@ __device__ void block_sum_to_result(double *red, int T, int width, int slot, int
     if (ticket != gridDim.x - 1) return;
     __threadfence();
     // last block: fixed-order sum over blocks, slot s handles blocks s, s+T, ...
+    // (four independent partial sums so the loads overlap)
     const int nb = gridDim.x;
     for (int k = tid; k < T * width; k += nt) {
         const int s = k / width, q = k - s * width;
-        double acc = 0.0;
-        for (int b = s; b < nb; b += T)
-            acc += __hip_atomic_load(&partial[(size_t)b * width + q], __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
-        red[k] = acc;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int b = s;
+        for (; b + 3 * T < nb; b += 4 * T) {
+            a0 += partial[(size_t)b * width + q];
+            a1 += partial[(size_t)(b + T) * width + q];
+            a2 += partial[(size_t)(b + 2 * T) * width + q];
+            a3 += partial[(size_t)(b + 3 * T) * width + q];
+        }
+        for (; b < nb; b += T) a0 += partial[(size_t)b * width + q];
+        red[k] = (a0 + a1) + (a2 + a3);
     }
     __syncthreads();
     for (int w = T >> 1; w > 0; w >>= 1) {

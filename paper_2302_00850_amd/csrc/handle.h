@@ -16,6 +16,7 @@ namespace cola {
 
 constexpr int kMaxRhs = 16;
 constexpr int kMaxGrid = 65536;
+constexpr int kReduceGrid = 2048;  // blocks of a launch that reduces
 
 struct TuneEntry {
     int rpt = 1;

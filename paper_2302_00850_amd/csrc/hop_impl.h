@@ -91,6 +91,14 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
                     }
                     expand_add(mu, sg, w, acc[r], eta);
                 }
+                // Register fence: the accumulators are final for this direction here, so
+                // the compiler cannot sink a direction's arithmetic to the end of the
+                // kernel (which kept every loaded spinor and link live at once).
+#pragma unroll
+                for (int r = 0; r < RPT; ++r)
+#pragma unroll
+                    for (int c = 0; c < 12; ++c)
+                        asm volatile("" : "+v"(acc[r][c].x), "+v"(acc[r][c].y));
             }
         }
 
@@ -163,10 +171,20 @@ template <SpinorFmt SF, LinkFmt LF, typename CR>
 hipError_t hop_launch_fmt(const HopArgs &a, int rpt, int grid, int block, hipStream_t st) {
     bool real_phase = true;
     for (int mu = 0; mu < 4; ++mu) real_phase &= a.phase[mu].y == 0.0;
+    // several rhs per lane only where the accumulators fit (FP64 keeps one)
+    constexpr bool multi = SF != SpinorFmt::F64;
     if (real_phase) {
         if (rpt == 1) return hop_launch_epi<SF, LF, CR, 1, true>(a, grid, block, st);
+        if constexpr (multi) {
+            if (rpt == 2) return hop_launch_epi<SF, LF, CR, 2, true>(a, grid, block, st);
+            if (rpt == 4) return hop_launch_epi<SF, LF, CR, 4, true>(a, grid, block, st);
+        }
     } else {
         if (rpt == 1) return hop_launch_epi<SF, LF, CR, 1, false>(a, grid, block, st);
+        if constexpr (multi) {
+            if (rpt == 2) return hop_launch_epi<SF, LF, CR, 2, false>(a, grid, block, st);
+            if (rpt == 4) return hop_launch_epi<SF, LF, CR, 4, false>(a, grid, block, st);
+        }
     }
     return hipErrorInvalidValue;
 }

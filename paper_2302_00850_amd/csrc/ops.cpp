@@ -143,6 +143,8 @@ int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, cons
     a.nrhs = nrhs;
     int groups, T, grid, block;
     shape_for(te, h->g.Vh, nrhs, &groups, &T, &grid, &block);
+    // launches that reduce keep the partial-sum array short (grid-stride instead)
+    if (c.norm_result && grid > kReduceGrid) grid = kReduceGrid;
     a.groups = groups;
     a.div_groups = make_fastdiv((uint32_t)groups);
     a.epi = c.epi;
@@ -166,8 +168,9 @@ int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, cons
 int tune_hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, TuneEntry *best,
              hipStream_t st) {
     std::vector<TuneEntry> cand;
-    for (int rpt : {1}) {
+    for (int rpt : {1, 2, 4}) {
         if (nrhs % rpt) continue;
+        if (rpt > 1 && spinor_fmt(prec) == SpinorFmt::F64) continue;
         const int G = nrhs / rpt;
         for (int T : {4, 8, 16, 32, 64, 128, 256}) {
             if (T * G > 256 || T * G < 64) continue;
