@@ -37,6 +37,9 @@ def _load():
     lib.oracle_hop_sites.argtypes = [_ip, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_long),
                                      ctypes.c_long, _dp, ctypes.c_int]
     lib.oracle_apply_M.argtypes = [_ip, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
+    lib.oracle_apply_M_sites.argtypes = [_ip, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp,
+                                         ctypes.POINTER(ctypes.c_long), ctypes.c_long, _dp,
+                                         ctypes.c_int]
     lib.oracle_apply_schur.argtypes = [_ip, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp,
                                        ctypes.c_int]
     lib.oracle_clover.argtypes = [_ip, ctypes.c_double, ctypes.c_double, _dp, _dp]
@@ -115,6 +118,17 @@ def hop_sites(U, psi, bc, sites, dagger=False):
     _load().oracle_hop_sites(_dims(U), _ptr(b), _ptr(U), _ptr(psi),
                              s.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), len(s), _ptr(out),
                              int(dagger))
+    return out
+
+
+def apply_M_sites(U, psi, kappa, bc, sites, csw=0.0, dagger=False):
+    """(M psi) at the given lexicographic sites only (clover built locally), shape (n,4,3)."""
+    U, psi, b = _arr(U), _arr(psi), _bc(bc)
+    s = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
+    out = np.empty((len(s), 4, 3), dtype=np.complex128)
+    _load().oracle_apply_M_sites(_dims(U), kappa, csw, _ptr(b), _ptr(U), _ptr(psi),
+                                 s.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), len(s),
+                                 _ptr(out), int(dagger))
     return out
 
 

@@ -346,6 +346,53 @@ void oracle_clover(const int L[4], double kappa, double csw, const double *Ud, d
     }
 }
 
+/*
+ * (M in)(x) at a list of sites only: A(x) in(x) - kappa (D in)(x), with the clover
+ * matrix A(x) (csw != 0) assembled at each listed site from its field strengths, as
+ * in oracle_clover.  dagger selects M^H = A - kappa D^H.
+ */
+void oracle_apply_M_sites(const int L[4], double kappa, double csw, const double *bc,
+                          const double *Ud, const double *ind, const long *sites, long n,
+                          double *outd, int dagger) {
+    const cplx *U = (const cplx *)Ud, *in = (const cplx *)ind;
+    cplx *out = (cplx *)outd;
+    cplx sigma[4][4][16];
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = 0; nu < 4; ++nu)
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    cplx c = 0;
+                    for (int k = 0; k < 4; ++k)
+                        c += GAMMA[mu][i][k] * GAMMA[nu][k][j] - GAMMA[nu][i][k] * GAMMA[mu][k][j];
+                    sigma[mu][nu][i * 4 + j] = 0.5 * I * c;
+                }
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k) {
+        const long s = sites[k];
+        cplx h[12], a[144];
+        hop_site(L, bc, U, in, s, h, dagger);
+        for (int q = 0; q < 144; ++q) a[q] = 0;
+        for (int q = 0; q < 12; ++q) a[q * 12 + q] = 1.0;
+        if (csw != 0.0)
+            for (int mu = 0; mu < 4; ++mu)
+                for (int nu = mu + 1; nu < 4; ++nu) {
+                    cplx F[9];
+                    field_strength(L, U, s, mu, nu, F);
+                    for (int si = 0; si < 4; ++si)
+                        for (int sj = 0; sj < 4; ++sj)
+                            for (int ci = 0; ci < 3; ++ci)
+                                for (int cj = 0; cj < 3; ++cj)
+                                    a[(si * 3 + ci) * 12 + sj * 3 + cj] -=
+                                        kappa * csw * sigma[mu][nu][si * 4 + sj] * F[ci * 3 + cj];
+                }
+        for (int i = 0; i < 12; ++i) {
+            cplx v = 0;
+            for (int j = 0; j < 12; ++j) v += a[i * 12 + j] * in[s * 12 + j];
+            out[k * 12 + i] = v - kappa * h[i];
+        }
+    }
+}
+
 /* per-site inverse of a 12x12 matrix field by Gauss-Jordan with partial pivoting; returns
  * 0, or -1 if a pivot vanished */
 int oracle_site_inverse(long nsites, const double *Ad, double *Bd) {

@@ -225,7 +225,11 @@ int cola_cg_solve(cola_handle_t *h, void *x, const void *b, int nrhs, const cola
     if (p->scheme < COLA_CG_FP64 || p->scheme > COLA_CG_FP32_DEFECT)
         return set_error(h, COLA_EINVAL, "unknown scheme");
     if (!(p->tol > 0) || p->max_iter < 1) return set_error(h, COLA_EINVAL, "bad tol / max_iter");
-    if (p->block) return set_error(h, COLA_EINVAL, "block CG is not available in this build");
+    if (p->block && (p->system == COLA_SYS_MDAGM ||
+                     (p->scheme != COLA_CG_FP16_DEFECT && p->scheme != COLA_CG_FP32_DEFECT)))
+        return set_error(h, COLA_EINVAL,
+                         "block CG runs as the inner solver of the defect-correction schemes on "
+                         "the even-odd systems");
     if (!h->gauge_set) return set_error(h, COLA_ESTATE, "no gauge field set");
     if (p->scheme != COLA_CG_FP64 && !h->su3)
         return set_error(h, COLA_EINVAL, "mixed-precision schemes need an SU(3) gauge field");

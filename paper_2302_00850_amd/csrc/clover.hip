@@ -160,7 +160,7 @@ __device__ void store_block(void *buf, int S, int p, uint32_t i, int blk, const 
             q[(size_t)(3 + r * (r - 1) / 2 + c) * S] = pr{(T)a[r * 6 + c].x, (T)a[r * 6 + c].y};
 }
 
-__global__ void clover_build_kernel(const Geom g, const C *__restrict__ U, double kappa, double csw,
+__global__ void __launch_bounds__(128) clover_build_kernel(const Geom g, const C *__restrict__ U, double kappa, double csw,
                                     void *a64, void *ainv64, void *a32, void *ainv32, int *bad) {
     const uint32_t V = 2u * (uint32_t)g.Vh;
     Lat lat;

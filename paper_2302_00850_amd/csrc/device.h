@@ -67,6 +67,17 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
     return (__umulhi(n, f.m) + n) >> f.s;
 }
 
+// Logical block index for an XCD-aware launch: workgroups are dispatched to the
+// 8 XCDs of the chip round-robin (block b runs on XCD b mod 8), so renumbering
+// b -> (b mod 8) * (grid / 8) + b / 8 (with the remainder spread over the first
+// XCDs) gives each XCD one contiguous range of the lattice, whose neighbour
+// spinors then stay in that XCD's own L2.  A permutation of [0, grid).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t grid) {
+    const uint32_t q = grid >> 3, rem = grid & 7u;
+    const uint32_t x = b & 7u, k = b >> 3;
+    return x * q + (x < rem ? x : rem) + k;
+}
+
 // Coordinates of checkerboard site i of parity p.
 __device__ __forceinline__ void site_coords(const Geom &g, uint32_t i, int p, int x[4]) {
     const uint32_t r0 = fdiv(i, g.div_xh);
@@ -155,6 +166,27 @@ struct SpinorBlock {
                 v[c] = {s * (float)h.x, s * (float)h.y};
             }
         } else {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const E h = data[c * SR + e];
+                v[c] = {h.x, h.y};
+            }
+        }
+    }
+
+    // The 12 components without the FP16 site scale; *scale receives it (1 otherwise).
+    __device__ __forceinline__ void load_unscaled(uint32_t i, uint32_t r, cpx<R> v[12],
+                                                  R *scale) const {
+        const uint32_t e = i * nrhs + r;
+        if constexpr (F == SpinorFmt::F16) {
+            *scale = norm[e];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const half2s h = data[c * SR + e];
+                v[c] = {(float)h.x, (float)h.y};
+            }
+        } else {
+            *scale = (R)1;
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 const E h = data[c * SR + e];
@@ -387,7 +419,9 @@ __device__ void block_sum_to_result(double *red, int T, int width, int slot, int
     const int nt = blockDim.x;
     for (int k = tid; k < T * width; k += nt) red[k] = 0.0;
     __syncthreads();
-    for (int k = 0; k < n; ++k) red[slot * width + q0 + k] = v[k];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)  // constant indices keep v in registers
+        if (k < n) red[slot * width + q0 + k] = v[k];
     __syncthreads();
     for (int w = T >> 1; w > 0; w >>= 1) {
         for (int k = tid; k < w * width; k += nt) red[k] += red[k + w * width];

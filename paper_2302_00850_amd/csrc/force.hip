@@ -17,7 +17,7 @@ namespace {
 
 using C = cpx<double>;
 
-__global__ void force_kernel(const Geom g, const void *gauge, const C *__restrict__ X,
+__global__ void __launch_bounds__(256) force_kernel(const Geom g, const void *gauge, const C *__restrict__ X,
                              const C *__restrict__ Y, C *__restrict__ F, double kappa,
                              Cplx64 ph0, Cplx64 ph1, Cplx64 ph2, Cplx64 ph3, int mode) {
     const uint32_t V = 2u * (uint32_t)g.Vh;

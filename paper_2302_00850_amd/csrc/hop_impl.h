@@ -43,7 +43,8 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     for (int r = 0; r < RPT; ++r) nrm[r] = 0.0;
 
     const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < a.total; t += stride) {
+    const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+    for (uint32_t t = lb * blockDim.x + threadIdx.x; t < a.total; t += stride) {
         const uint32_t i = fdiv(t, a.div_groups);
         const uint32_t j = t - i * (uint32_t)a.groups;
         int x[4];
@@ -76,7 +77,8 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
                     C s[12], h[6], w[6];
-                    in.load(n, j * RPT + r, s);
+                    T scl;  // FP16 site scale, applied with the phase after the multiply
+                    in.load_unscaled(n, j * RPT + r, s, &scl);
                     project(mu, sg, s, h);
                     if (dir == 0) {
                         su3_mul(u, h, w);
@@ -89,7 +91,7 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
 #pragma unroll
                         for (int k = 0; k < 6; ++k) w[k] = cmul(ph, w[k]);
                     }
-                    expand_add(mu, sg, w, acc[r], eta);
+                    expand_add(mu, sg, w, acc[r], SF == SpinorFmt::F16 ? eta * scl : eta);
                 }
                 // Register fence: the accumulators are final for this direction here, so
                 // the compiler cannot sink a direction's arithmetic to the end of the

@@ -65,6 +65,17 @@ hipError_t launch_residual(const BlasShape &b, void *r, const void *bb, const vo
 hipError_t launch_clover_site(const BlasShape &b, SpinorFmt f, int clov_double, void *out,
                               const void *in, const void *clov, int parity, hipStream_t st);
 
+// --- block CG on n <= 16 rhs of one packed block (stride S)
+// red.result receives G transposed: (b * n + a) * 2 + {re, im} = sum conj(A_a) B_b
+hipError_t launch_gram(int S, int n, SpinorFmt fa, SpinorFmt fb, const void *A, const void *B,
+                       const Reduce &red, hipStream_t st);
+// X_b += sum_a P_a alpha_ab, R_b -= sum_a Q_a alpha_ab (alpha row-major complex FP64)
+hipError_t launch_block_axpy(int S, int n, SpinorFmt fx, SpinorFmt fp, void *X, const void *P,
+                             void *R, const void *Q, const double *alpha, hipStream_t st);
+// Pn_b = R_b + sum_a P_a beta_ab
+hipError_t launch_block_xpay(int S, int n, SpinorFmt fr, SpinorFmt fp, void *Pn, const void *R,
+                             const void *P, const double *beta, hipStream_t st);
+
 // --- clover
 // Builds A = 1 - kappa csw sum sigma F (two 6x6 chiral blocks) and A^-1 per site from
 // the canonical FP64 links; writes FP64 and FP32 packed copies.  bad counts sites

@@ -101,13 +101,29 @@ def _check_dims(dims):
 
 
 class Synth:
-    """One seeded stream of synthetic fields (numpy PCG64 draws)."""
+    """One seeded stream of synthetic fields.
 
-    def __init__(self, seed: int = 0, device="cpu"):
-        self.rng = np.random.default_rng(seed)
+    rng="numpy" (default): numpy PCG64 draws, identical on every machine.
+    rng="torch": draws from a torch.Generator on `device` (fast for 10^7-site
+    lattices; reproducible for a given device type, not across them).
+    """
+
+    def __init__(self, seed: int = 0, device="cpu", rng: str = "numpy"):
         self.device = torch.device(device)
+        self.kind = rng
+        if rng == "numpy":
+            self.rng = np.random.default_rng(seed)
+        elif rng == "torch":
+            self.gen = torch.Generator(device=self.device)
+            self.gen.manual_seed(seed)
+        else:
+            raise ValueError("rng must be 'numpy' or 'torch'")
 
     def _complex_normal(self, shape, std):
+        if self.kind == "torch":
+            re = torch.randn(shape, generator=self.gen, dtype=torch.float64, device=self.device)
+            im = torch.randn(shape, generator=self.gen, dtype=torch.float64, device=self.device)
+            return torch.complex(re, im) * std
         re = self.rng.standard_normal(shape)
         im = self.rng.standard_normal(shape)
         z = torch.complex(torch.from_numpy(re), torch.from_numpy(im)).to(self.device)

@@ -1,0 +1,220 @@
+"""Full-size checks at the workload lattices, in the launch configuration the
+benchmark uses:
+
+* hop / M (with clover) outputs on sampled sites against the oracle's per-site
+  evaluation (32^3x64 FP16 x 12 rhs and FP32, 48^3x96 clover FP32 and FP64);
+* the free-field propagator at 32^3x64 against its closed form in momentum
+  space (FFT), for the FP64 and FP16-defect solvers;
+* the fermion force at 24^3x48 against a local-resolvent central finite
+  difference on 64 links and against the oracle's force on every link.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import dense
+from paper_2302_00850_amd.synth import Synth, bc_phases, point_sources, unit_gauge
+from tests._util import rel
+
+pytestmark = pytest.mark.gpu
+
+cola = pytest.importorskip("paper_2302_00850_amd.cola")
+
+ANTI = bc_phases((0, 0, 0, np.pi))
+
+
+def _lex_parity(dims, sites):
+    lx, ly, lz, lt = dims
+    s = np.asarray(sites)
+    x = s % lx
+    y = (s // lx) % ly
+    z = (s // (lx * ly)) % lz
+    t = s // (lx * ly * lz)
+    return (x + y + z + t) % 2
+
+
+def _sample_sites(dims, parity, n, seed):
+    rng = np.random.default_rng(seed)
+    V = int(np.prod(dims))
+    cand = rng.choice(V, size=4 * n, replace=False)
+    cand = cand[_lex_parity(dims, cand) == parity][:n - 2]
+    # always include the two corners of the lattice (boundary hops)
+    corners = np.array([0, V - 1])
+    corners = corners[_lex_parity(dims, corners) == parity]
+    return np.concatenate([cand, corners])
+
+
+@pytest.mark.parametrize("prec,nrhs,tol", [(3, 12, 4e-3), (2, 1, 2e-6), (0, 1, 1e-13)])
+def test_hop_sampled_32x64(prec, nrhs, tol):
+    dims = (32, 32, 32, 64)
+    s = Synth(7, device="cuda", rng="torch")
+    U = s.gauge(dims)
+    psi = s.gaussian_spinor(dims, nrhs)
+    lat = cola.Lattice(dims, 0.12, ANTI)
+    lat.set_gauge(U)
+    parity = 0
+    pin = lat.pack(psi, prec, 1 - parity)
+    out = lat.empty_packed(prec, nrhs, parity)
+    lat.dslash(out, pin, cola.COLA_OP_HOP, parity, prec, nrhs)
+    got = lat.unpack(out, prec, nrhs, parity).cpu().numpy()
+    src = lat.unpack(pin, prec, nrhs, 1 - parity).cpu().numpy()
+    Uh = U.cpu().numpy()
+    sites = _sample_sites(dims, parity, 256, 1)
+    for q in range(nrhs):
+        ref = oracle.hop_sites(Uh, src[q], ANTI, sites)
+        g = got[q].reshape(-1, 4, 3)[sites]
+        assert rel(g, ref) <= tol, (prec, q)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-13), (2, 2e-6)])
+def test_clover_M_sampled_48x96(prec, tol):
+    dims = (48, 48, 48, 96)
+    kappa, csw = 0.118, 1.0
+    s = Synth(8, device="cuda", rng="torch")
+    U = s.gauge(dims)
+    psi = s.gaussian_spinor(dims, 1)
+    lat = cola.Lattice(dims, kappa, ANTI, csw)
+    lat.set_gauge(U)
+    pin = lat.pack(psi, prec, -1)
+    out = lat.empty_packed(prec, 1, -1)
+    lat.dslash(out, pin, cola.COLA_OP_M, -1, prec, 1)
+    got = lat.unpack(out, prec, 1, -1).cpu().numpy()[0].reshape(-1, 4, 3)
+    src = lat.unpack(pin, prec, 1, -1).cpu().numpy()[0]
+    del out, pin
+    Uh = U.cpu().numpy()
+    sites = np.concatenate([_sample_sites(dims, 0, 128, 2), _sample_sites(dims, 1, 128, 3)])
+    ref = oracle.apply_M_sites(Uh, src, kappa, ANTI, sites, csw=csw)
+    assert rel(got[sites], ref) <= tol
+
+
+def _free_prop(b, dims, kappa, theta=(0, 0, 0, np.pi)):
+    """(M^H M)^{-1} b at U = 1 from the momentum-space symbol a^2 + |b|^2."""
+    lx, ly, lz, lt = dims
+    t, z, y, x = np.meshgrid(np.arange(lt), np.arange(lz), np.arange(ly), np.arange(lx),
+                             indexing="ij")
+    w = np.exp(1j * (theta[0] * x / lx + theta[1] * y / ly + theta[2] * z / lz
+                     + theta[3] * t / lt))[..., None, None]
+    bt = np.fft.fftn(b / w, axes=(0, 1, 2, 3))
+    p = [(2 * np.pi * x + theta[0]) / lx, (2 * np.pi * y + theta[1]) / ly,
+         (2 * np.pi * z + theta[2]) / lz, (2 * np.pi * t + theta[3]) / lt]
+    a = 1 - 2 * kappa * sum(np.cos(pm) for pm in p)
+    lam = a * a + sum((2 * kappa * np.sin(pm)) ** 2 for pm in p)
+    return np.fft.ifftn(bt / lam[..., None, None], axes=(0, 1, 2, 3)) * w
+
+
+def test_free_field_propagator_32x64():
+    """U = 1 at the multi-RHS workload's shape: GPU solves of M^H M x = b match the
+    FFT closed form (FP64 CG on a Gaussian source; FP16 defect correction on 2 of
+    the point sources, full lattice)."""
+    dims = (32, 32, 32, 64)
+    kappa = 0.12
+    lat = cola.Lattice(dims, kappa, ANTI)
+    lat.set_gauge(unit_gauge(dims, device="cuda"))
+    b = Synth(9, device="cuda", rng="torch").gaussian_spinor(dims, 1)
+    x, info = lat.cg(b, system=cola.COLA_SYS_MDAGM, scheme=cola.COLA_CG_FP64, tol=1e-10)
+    assert info["status"] == cola.COLA_OK
+    ref = _free_prop(b.cpu().numpy()[0], dims, kappa)
+    # cond(M^H M) ~ 2e3 at kappa = 0.12: forward error <= cond * tol
+    assert rel(x.cpu().numpy()[0], ref) < 3e-7
+    pts = point_sources(dims, device="cuda")[[0, 7]].contiguous()
+    x, info = lat.cg(pts, system=cola.COLA_SYS_MDAGM, scheme=cola.COLA_CG_FP16_DEFECT, tol=1e-10)
+    assert info["status"] == cola.COLA_OK, info
+    xs = x.cpu().numpy()
+    p = pts.cpu().numpy()
+    for q in range(2):
+        assert rel(xs[q], _free_prop(p[q], dims, kappa)) < 3e-7
+
+
+def _link_sites(site, mu, dims):
+    """Array indices (t,z,y,x) of x and x + mu, and whether the hop crosses the edge."""
+    lx, ly, lz, lt = dims
+    c = np.array(np.unravel_index(site, (lt, lz, ly, lx)))[::-1]  # x, y, z, t
+    cf = c.copy()
+    cf[mu] = (cf[mu] + 1) % dims[mu]
+    return (tuple(int(v) for v in c[::-1]), tuple(int(v) for v in cf[::-1]),
+            c[mu] == dims[mu] - 1)
+
+
+def _deltaM_apply(v_x, v_f, dU, mu, edge, kappa, bc):
+    """(dM v) at x and at x + mu for a change dU of the link U_mu(x); dM = -kappa dD."""
+    g = dense.gammas()
+    ef = complex(*bc[mu]) if edge else 1.0
+    one = np.eye(4)
+    at_x = -kappa * ef * (one - g[mu]) @ (v_f @ dU.T)
+    at_f = -kappa * np.conj(ef) * (one + g[mu]) @ (v_x @ dU.conj())
+    return at_x, at_f
+
+
+def test_force_fd_and_oracle_24x48():
+    """S = phi^H (M^H M)^{-1} phi, phi = M^H eta at 24^3x48, kappa 0.12:
+    (1) GPU force from GPU solves equals the oracle force on the same X, Y;
+    (2) Y = eta; (3) on 64 random links, a local-resolvent central difference
+    Delta S(+-e) = -[(dM X')^H Y + Y'^H (dM X)] (exact in e, no cancellation of S)
+    matches Tr(H F) to 1e-8 of the RMS derivative."""
+    dims = (24, 24, 24, 48)
+    kappa = 0.12
+    s = Synth(10, device="cuda", rng="torch")
+    U = s.gauge(dims)
+    eta = s.gaussian_spinor(dims, 1)
+    lat = cola.Lattice(dims, kappa, ANTI)
+    lat.set_gauge(U)
+    ep = lat.pack(eta, cola.COLA_FP64, -1)
+    php = lat.empty_packed(cola.COLA_FP64, 1, -1)
+    lat.dslash(php, ep, cola.COLA_OP_MDAG, -1, cola.COLA_FP64, 1)
+    phi = lat.unpack(php, cola.COLA_FP64, 1, -1)
+    X, info = lat.cg(phi, system=cola.COLA_SYS_MDAGM, tol=1e-12)
+    assert info["status"] == cola.COLA_OK
+
+    def apply_m(v):
+        vp = lat.pack(v, cola.COLA_FP64, -1)
+        o = lat.empty_packed(cola.COLA_FP64, 1, -1)
+        lat.dslash(o, vp, cola.COLA_OP_M, -1, cola.COLA_FP64, 1)
+        return lat.unpack(o, cola.COLA_FP64, 1, -1)
+
+    Y = apply_m(X)
+    assert rel(Y.cpu().numpy(), eta.cpu().numpy()) < 1e-9
+    F = lat.force(X[0], Y[0], cola.COLA_FORCE_LIE).cpu().numpy()
+    G = lat.force(X[0], Y[0], cola.COLA_FORCE_GRAD).cpu().numpy()
+    Uh = U.cpu().numpy()
+    Xh, Yh = X.cpu().numpy()[0], Y.cpu().numpy()[0]
+    assert rel(G, oracle.force(Uh, Xh, Yh, kappa, ANTI, mode=0)) <= 1e-12
+    assert rel(F, oracle.force(Uh, Xh, Yh, kappa, ANTI, mode=1)) <= 1e-12
+
+    rng = np.random.default_rng(11)
+    V = int(np.prod(dims))
+    eps = 1e-5
+    D, pred = [], []
+    Ug = U.clone()
+    for k in range(64):
+        site = int(rng.integers(V))
+        mu = int(rng.integers(4))
+        h = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+        H = 0.5 * (h + h.conj().T)
+        H -= np.trace(H) / 3 * np.eye(3)
+        ix, ifw, edge = _link_sites(site, mu, dims)
+        idx = ix + (mu,)
+        ev, vec = np.linalg.eigh(H)
+        dS = []
+        for sgn in (1.0, -1.0):
+            # dU = (exp(i e H) - 1) U via expm1 of the eigenvalues (no cancellation)
+            dU = (vec * np.expm1(1j * sgn * eps * ev)) @ vec.conj().T @ Uh[idx]
+            Ug[idx] = torch.from_numpy(Uh[idx] + dU).cuda()
+            lat.set_gauge(Ug)
+            Xp, inf = lat.cg(phi, system=cola.COLA_SYS_MDAGM, tol=1e-12, x0=X)
+            assert inf["status"] == cola.COLA_OK
+            Yp = apply_m(Xp)
+            xp_x, xp_f = Xp[0][ix].cpu().numpy(), Xp[0][ifw].cpu().numpy()
+            yp_x, yp_f = Yp[0][ix].cpu().numpy(), Yp[0][ifw].cpu().numpy()
+            dmx = _deltaM_apply(Xh[ix], Xh[ifw], dU, mu, edge, kappa, ANTI)
+            dmxp = _deltaM_apply(xp_x, xp_f, dU, mu, edge, kappa, ANTI)
+            val = -(np.vdot(dmxp[0], Yh[ix]).real + np.vdot(dmxp[1], Yh[ifw]).real
+                    + np.vdot(yp_x, dmx[0]).real + np.vdot(yp_f, dmx[1]).real)
+            dS.append(val)
+        Ug[idx] = U[idx]
+        D.append((dS[0] - dS[1]) / (2 * eps))
+        pred.append(np.trace(H @ F[idx]).real)
+    lat.set_gauge(U)
+    D, pred = np.array(D), np.array(pred)
+    rms = np.sqrt(np.mean(D ** 2))
+    assert np.max(np.abs(D - pred)) <= 1e-8 * rms, (np.max(np.abs(D - pred)), rms)

@@ -94,6 +94,51 @@ def test_cg_schemes_reach_tolerance(fields, scheme, system, nrhs):
         assert np.all(np.where(_even(DIMS), 0, xs) == 0)
 
 
+@pytest.mark.parametrize("scheme", [cola.COLA_CG_FP16_DEFECT, cola.COLA_CG_FP32_DEFECT])
+@pytest.mark.parametrize("system", [cola.COLA_SYS_SCHUR, cola.COLA_SYS_PROPAGATOR])
+def test_block_cg_reaches_tolerance(fields, scheme, system):
+    """Block CG (one Krylov space for the 12 point sources) inside defect correction."""
+    U, b = fields
+    src = point_sources(DIMS).numpy()
+    lat = _lat(U, ANTI)
+    x, info = lat.cg(_cuda(src), system=system, scheme=scheme, tol=1e-10, block=1)
+    assert info["status"] == cola.COLA_OK, info
+    xs = x.cpu().numpy()
+    for q in range(12):
+        if system == cola.COLA_SYS_SCHUR:
+            r = _normal_residual(U, xs[q], src[q], system, KAPPA, ANTI)
+            assert r <= 1.05e-10, (q, r, info)
+        else:
+            assert rel(oracle.apply_M(U, xs[q], KAPPA, ANTI), src[q]) < 1e-8
+    # lockstep twin: the same solutions (to the solver tolerance, relative to cond)
+    x2, info2 = lat.cg(_cuda(src), system=system, scheme=scheme, tol=1e-10, block=0)
+    assert rel(xs, x2.cpu().numpy()) < 1e-7
+
+
+def test_block_cg_dependent_columns(fields):
+    """Duplicate and zero columns make the block Gram matrices singular; the
+    deflating small solve must still converge every column."""
+    U, b = fields
+    src = np.stack([b[0], b[1], b[0], np.zeros_like(b[0]), 2.0 * b[1]])
+    lat = _lat(U, ANTI)
+    x, info = lat.cg(_cuda(src), system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP32_DEFECT,
+                     tol=1e-10, block=1)
+    assert info["status"] == cola.COLA_OK, info
+    xs = x.cpu().numpy()
+    assert np.all(xs[3] == 0)
+    for q in (0, 1, 2, 4):
+        assert _normal_residual(U, xs[q], src[q], cola.COLA_SYS_SCHUR, KAPPA, ANTI) <= 1.05e-10
+
+
+def test_block_cg_rejected_where_unsupported(fields):
+    U, b = fields
+    lat = _lat(U, ANTI)
+    with pytest.raises(cola.ColaError):
+        lat.cg(_cuda(b[:2]), system=cola.COLA_SYS_MDAGM, scheme=cola.COLA_CG_FP16_DEFECT, block=1)
+    with pytest.raises(cola.ColaError):
+        lat.cg(_cuda(b[:2]), system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP64, block=1)
+
+
 @pytest.mark.parametrize("scheme", [cola.COLA_CG_FP64, cola.COLA_CG_FP32_DEFECT])
 def test_cg_clover_schur(fields, scheme):
     U, b = fields

@@ -181,3 +181,25 @@ def test_force_gauge_covariance():
     FG = oracle.force(UG, XG, YG, 0.12, ANTIPERIODIC, mode=1)
     expect = G[..., None, :, :] @ F @ G[..., None, :, :].conj().swapaxes(-1, -2)
     assert rel(FG, expect) < 1e-13
+
+
+def test_local_resolvent_difference_is_exact(tiny):
+    """Delta S = S(U') - S(U) = -[(dM X')^H Y + Y'^H (dM X)] with Y = M X, Y' = M' X'
+    (exact in dM), checked against dense actions; it is the finite-difference form
+    used at full size, where S itself is too large to difference in FP64."""
+    U, phi, kappa = tiny
+    M = dense.wilson_matrix(U, kappa, GENERIC)
+    X = np.linalg.solve(M.conj().T @ M, dense.to_vec(phi))
+    Y = M @ X
+    rng = np.random.default_rng(3)
+    Up = U.copy()
+    idx = (1, 0, 1, 0, 2)
+    h = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+    Up[idx] = expm(0.05j * (h + h.conj().T)) @ U[idx]
+    Mp = dense.wilson_matrix(Up, kappa, GENERIC)
+    Xp = np.linalg.solve(Mp.conj().T @ Mp, dense.to_vec(phi))
+    Yp = Mp @ Xp
+    dM = Mp - M
+    dS = -(np.vdot(dM @ Xp, Y) + np.vdot(Yp, dM @ X)).real
+    direct = dense.action(Up, phi, kappa, GENERIC) - dense.action(U, phi, kappa, GENERIC)
+    assert abs(dS - direct) < 1e-10 * abs(direct)
