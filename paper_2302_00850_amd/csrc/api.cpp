@@ -24,9 +24,11 @@ bool valid_prec(int p) { return p >= COLA_FP64 && p <= COLA_FP16; }
 int check_rhs(cola_handle_t *h, int nrhs) {
     if (nrhs < 1 || nrhs > kMaxRhs)
         return set_error(h, COLA_EINVAL, "nrhs must be in 1.." + std::to_string(kMaxRhs));
-    // element offsets are 32-bit inside the kernels
-    if ((double)h->g.S * nrhs * 12.0 >= 4294967296.0)
-        return set_error(h, COLA_EINVAL, "lattice x nrhs too large for 32-bit element offsets");
+    // element offsets are 32-bit inside the kernels and one buffer descriptor spans
+    // one component array of a block (S * nrhs elements of at most 16 bytes)
+    if ((double)h->g.S * nrhs * 12.0 >= 4294967296.0 ||
+        (double)h->g.S * nrhs * 16.0 >= 2147483648.0)
+        return set_error(h, COLA_EINVAL, "lattice x nrhs too large for 32-bit offsets");
     return COLA_OK;
 }
 

@@ -140,6 +140,59 @@ struct SpinorT<SpinorFmt::F16> {
     using elem = half2s;
 };
 
+// Loads and stores go through buffer resources: one descriptor per component
+// array (base = the array, size = its bytes), the per-lane byte offset of the
+// site in a VGPR.  Every component of a site then shares one VGPR offset and the
+// component base lives in scalar registers, so no per-lane 64-bit address
+// arithmetic is spent per load; accesses beyond the descriptor size read zero
+// and drop stores.  Arrays handed to one descriptor are below 2^31 bytes
+// (checked on the host).
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+template <typename E>
+__device__ __forceinline__ E bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    E v;
+    if constexpr (sizeof(E) == 2) {
+        const unsigned short w = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+        __builtin_memcpy(&v, &w, 2);
+    } else if constexpr (sizeof(E) == 4) {
+        const unsigned int w = __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+        __builtin_memcpy(&v, &w, 4);
+    } else if constexpr (sizeof(E) == 8) {
+        const u32x2_t w = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+        __builtin_memcpy(&v, &w, 8);
+    } else {
+        static_assert(sizeof(E) == 16, "16-byte element");
+        const u32x4_t w = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+        __builtin_memcpy(&v, &w, 16);
+    }
+    return v;
+}
+
+template <typename E>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, const E &v) {
+    if constexpr (sizeof(E) == 4) {
+        unsigned int w;
+        __builtin_memcpy(&w, &v, 4);
+        __builtin_amdgcn_raw_buffer_store_b32(w, r, (int)off, 0, 0);
+    } else if constexpr (sizeof(E) == 8) {
+        u32x2_t w;
+        __builtin_memcpy(&w, &v, 8);
+        __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)off, 0, 0);
+    } else {
+        static_assert(sizeof(E) == 16, "16-byte element");
+        u32x4_t w;
+        __builtin_memcpy(&w, &v, 16);
+        __builtin_amdgcn_raw_buffer_store_b128(w, r, (int)off, 0, 0);
+    }
+}
+
 // View of one parity block of a packed spinor field.
 template <SpinorFmt F>
 struct SpinorBlock {
@@ -147,7 +200,7 @@ struct SpinorBlock {
     using R = typename SpinorT<F>::real;
     E *data;
     float *norm;     // FP16 only
-    uint32_t SR;     // S * nrhs: distance between components
+    uint32_t SR;     // S * nrhs: distance between components (elements)
     uint32_t nrhs;
 
     __device__ __forceinline__ SpinorBlock(const void *base, int S, int nr)
@@ -155,22 +208,17 @@ struct SpinorBlock {
         if (F == SpinorFmt::F16) norm = (float *)(data + 12 * (size_t)SR);
     }
 
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t comp(int c) const {
+        return buf(data + (size_t)c * SR, SR * (uint32_t)sizeof(E));
+    }
+
     // the 12 components of site i, rhs r, in compute precision
     __device__ __forceinline__ void load(uint32_t i, uint32_t r, cpx<R> v[12]) const {
-        const uint32_t e = i * nrhs + r;
+        R s;
+        load_unscaled(i, r, v, &s);
         if constexpr (F == SpinorFmt::F16) {
-            const float s = norm[e];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                const half2s h = data[c * SR + e];
-                v[c] = {s * (float)h.x, s * (float)h.y};
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                const E h = data[c * SR + e];
-                v[c] = {h.x, h.y};
-            }
+            for (int c = 0; c < 12; ++c) v[c] = {s * v[c].x, s * v[c].y};
         }
     }
 
@@ -178,43 +226,43 @@ struct SpinorBlock {
     __device__ __forceinline__ void load_unscaled(uint32_t i, uint32_t r, cpx<R> v[12],
                                                   R *scale) const {
         const uint32_t e = i * nrhs + r;
+        const uint32_t off = e * (uint32_t)sizeof(E);
         if constexpr (F == SpinorFmt::F16) {
-            *scale = norm[e];
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                const half2s h = data[c * SR + e];
-                v[c] = {(float)h.x, (float)h.y};
-            }
+            *scale = bload<float>(buf(norm, SR * 4u), e * 4u);
         } else {
             *scale = (R)1;
+        }
 #pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                const E h = data[c * SR + e];
-                v[c] = {h.x, h.y};
-            }
+        for (int c = 0; c < 12; ++c) {
+            const E h = bload<E>(comp(c), off);
+            v[c] = {(R)h.x, (R)h.y};
         }
     }
 
     // Store; v is replaced by the values actually stored (FP16 rounding).
     __device__ __forceinline__ void store(uint32_t i, uint32_t r, cpx<R> v[12]) const {
         const uint32_t e = i * nrhs + r;
+        const uint32_t off = e * (uint32_t)sizeof(E);
         if constexpr (F == SpinorFmt::F16) {
             float m = 0.f;
 #pragma unroll
             for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].x), fabsf(v[c].y)));
+            // a site whose largest entry is below 1e-30 is stored as zero: 1/m would
+            // overflow for FP32 denormals (point-source propagators decay that far)
+            if (!(m >= 1e-30f) && m == m) m = 0.f;
             const float inv = m > 0.f ? 1.0f / m : 0.f;
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 half2s h;
                 h.x = (_Float16)(v[c].x * inv);
                 h.y = (_Float16)(v[c].y * inv);
-                data[c * SR + e] = h;
+                bstore<E>(comp(c), off, h);
                 v[c] = {m * (float)h.x, m * (float)h.y};
             }
-            norm[e] = m;
+            bstore<float>(buf(norm, SR * 4u), e * 4u, m);
         } else {
 #pragma unroll
-            for (int c = 0; c < 12; ++c) data[c * SR + e] = E{v[c].x, v[c].y};
+            for (int c = 0; c < 12; ++c) bstore<E>(comp(c), off, E{v[c].x, v[c].y});
         }
     }
 };
@@ -251,24 +299,25 @@ __device__ __forceinline__ void load_link(const void *gauge, int S, int p, int m
                                           cpx<T> u[3][3]) {
     using CH = typename LinkT<F>::chunk;
     constexpr int N = link_chunks(F);
-    const CH *base = (const CH *)gauge + ((size_t)(p * 4 + mu) * N) * (size_t)S + i;
+    const CH *base = (const CH *)gauge + ((size_t)(p * 4 + mu) * N) * (size_t)S;  // uniform
+    const uint32_t off = i * (uint32_t)sizeof(CH);
     if constexpr (F == LinkFmt::F64_18) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const CH c = base[(size_t)k * S];
+            const CH c = bload<CH>(buf(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
             u[k / 3][k % 3] = {(T)c.a, (T)c.b};
         }
         return;
     } else if constexpr (F == LinkFmt::F64_12) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const CH c = base[(size_t)k * S];
+            const CH c = bload<CH>(buf(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
             u[k / 3][k % 3] = {(T)c.a, (T)c.b};
         }
     } else {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const CH c = base[(size_t)k * S];
+            const CH c = bload<CH>(buf(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
             u[(2 * k) / 3][(2 * k) % 3] = {(T)c.a, (T)c.b};
             u[(2 * k + 1) / 3][(2 * k + 1) % 3] = {(T)c.c, (T)c.d};
         }
@@ -371,7 +420,8 @@ template <typename CR, typename T>
 __device__ __forceinline__ void clover_apply(const void *clov, int S, int p, uint32_t i,
                                              const cpx<T> in[12], cpx<T> out[12]) {
     struct pair { CR a, b; };
-    const pair *base = (const pair *)clov + (size_t)(p * 36) * S + i;
+    const pair *base = (const pair *)clov + (size_t)(p * 36) * S;  // uniform
+    const uint32_t off = i * (uint32_t)sizeof(pair);
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
         const pair *q = base + (size_t)(blk * 18) * S;
@@ -379,13 +429,13 @@ __device__ __forceinline__ void clover_apply(const void *clov, int S, int p, uin
         cpx<T> o[15];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const pair v = q[(size_t)k * S];
+            const pair v = bload<pair>(buf(q + (size_t)k * S, (uint32_t)S * sizeof(pair)), off);
             d[2 * k] = (T)v.a;
             d[2 * k + 1] = (T)v.b;
         }
 #pragma unroll
         for (int k = 0; k < 15; ++k) {
-            const pair v = q[(size_t)(3 + k) * S];
+            const pair v = bload<pair>(buf(q + (size_t)(3 + k) * S, (uint32_t)S * sizeof(pair)), off);
             o[k] = {(T)v.a, (T)v.b};
         }
         const cpx<T> *v = in + 6 * blk;
