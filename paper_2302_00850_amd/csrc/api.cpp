@@ -277,9 +277,11 @@ size_t cola_tune_dump(const cola_handle_t *h, char *buf, size_t len) {
     bool first = true;
     for (auto &kv : h->tune) {
         char e[256];
-        snprintf(e, sizeof e, "%s\"%s\": {\"rpt\": %d, \"sites_per_block\": %d, \"grid\": %d, \"ms\": %.6f}",
+        snprintf(e, sizeof e,
+                 "%s\"%s\": {\"rpt\": %d, \"sites_per_block\": %d, \"grid\": %d, "
+                 "\"tchunk\": %d, \"ms\": %.6f}",
                  first ? "" : ", ", kv.first.c_str(), kv.second.rpt, kv.second.sites_per_block,
-                 kv.second.grid, kv.second.ms);
+                 kv.second.grid, kv.second.tchunk, kv.second.ms);
         s += e;
         first = false;
     }

@@ -24,25 +24,24 @@ struct Loc {
     uint32_t blk, i, r;
 };
 
+// The parity block of a lane is blockIdx.y, so every view is wavefront-uniform.
 template <SpinorFmt F>
-__device__ __forceinline__ SpinorBlock<F> view(const void *base, size_t bb, const Loc &l, int S,
-                                               int R) {
-    return SpinorBlock<F>((const char *)base + l.blk * bb, S, R);
+__device__ __forceinline__ SpinorBlock<F, true> view(const void *base, size_t bb, const Loc &l,
+                                                     int S, int R) {
+    return SpinorBlock<F, true>((const char *)base + l.blk * bb, S, R);
 }
 
-// Generic grid-stride driver: f(loc) returns this lane's contribution to the
-// per-rhs reduction (ignored when red.result is null).
+// Generic grid-stride driver over one parity block per grid row (blockIdx.y):
+// f(loc) returns this lane's contribution to the per-rhs reduction (ignored when
+// red.result is null).
 template <class Fn>
 __global__ void __launch_bounds__(256) site_kernel(Fn f, const BlasShape sh, const Reduce red) {
     extern __shared__ double lds[];
     const uint32_t SR = (uint32_t)sh.S * sh.R;
-    const uint32_t total = SR * (uint32_t)sh.nblk;
     double acc[1] = {0.0};
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += gridDim.x * blockDim.x) {
-        Loc l;
-        l.blk = t / SR;
-        const uint32_t e = t - l.blk * SR;
+    Loc l;
+    l.blk = blockIdx.y;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < SR; e += gridDim.x * blockDim.x) {
         l.i = e / (uint32_t)sh.R;
         l.r = e - l.i * (uint32_t)sh.R;
         acc[0] += f(l);
@@ -51,7 +50,8 @@ __global__ void __launch_bounds__(256) site_kernel(Fn f, const BlasShape sh, con
         const int slot = threadIdx.x / sh.R;
         const int q = threadIdx.x - slot * sh.R;
         block_sum_to_result<1>(lds, sh.T, sh.R, slot, q, 1, acc, red.partial, red.counter,
-                               red.result);
+                               red.result, blockIdx.y * gridDim.x + blockIdx.x,
+                               gridDim.x * gridDim.y);
     }
 }
 
@@ -59,7 +59,8 @@ template <class Fn>
 hipError_t run(const Fn &f, const BlasShape &sh, const Reduce *red, hipStream_t st) {
     Reduce r = red ? *red : Reduce{nullptr, nullptr, nullptr};
     const size_t shm = r.result ? (size_t)sh.T * sh.R * sizeof(double) : 0;
-    hipLaunchKernelGGL(site_kernel<Fn>, dim3(sh.grid), dim3(sh.T * sh.R), shm, st, f, sh, r);
+    hipLaunchKernelGGL(site_kernel<Fn>, dim3(sh.grid, sh.nblk), dim3(sh.T * sh.R), shm, st, f,
+                       sh, r);
     return hipGetLastError();
 }
 
@@ -253,7 +254,7 @@ BlasShape blas_shape(const Geom &g, int nrhs, int nblk) {
     int T = 1;
     while (T * 2 * nrhs <= 256) T *= 2;
     b.T = T;
-    const size_t work = (size_t)g.S * nrhs * nblk;
+    const size_t work = (size_t)g.S * nrhs;  // per parity block (grid row)
     size_t grid = (work + (size_t)T * nrhs - 1) / ((size_t)T * nrhs);
     if (grid > 2048) grid = 2048;  // grid-stride; keeps the partial-sum array short
     b.grid = (int)(grid < 1 ? 1 : grid);

@@ -23,7 +23,7 @@ size_t bbytes(SpinorFmt f, int S, int R) {
 
 // component c of (site i, rhs r) in compute precision
 template <SpinorFmt F>
-__device__ __forceinline__ cpx<typename SpinorT<F>::real> comp(const SpinorBlock<F> &v, int c,
+__device__ __forceinline__ cpx<typename SpinorT<F>::real> comp(const SpinorBlock<F, true> &v, int c,
                                                               uint32_t i, uint32_t r) {
     const uint32_t e = i * v.nrhs + r;
     const auto h = v.data[c * v.SR + e];
@@ -41,8 +41,8 @@ template <SpinorFmt FA, SpinorFmt FB>
 __global__ void __launch_bounds__(256) gram_kernel(const void *A, const void *B, int S, int n,
                                                    int T, Reduce red) {
     extern __shared__ double lds[];
-    const SpinorBlock<FA> va(A, S, n);
-    const SpinorBlock<FB> vb(B, S, n);
+    const SpinorBlock<FA, true> va(A, S, n);
+    const SpinorBlock<FB, true> vb(B, S, n);
     double acc[2 * kMaxN];
 #pragma unroll
     for (int k = 0; k < 2 * kMaxN; ++k) acc[k] = 0.0;
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(256) gram_kernel(const void *A, const void *B,
     }
     // result layout: index (b * n + a) * 2 + {re, im} holds G_ab
     block_sum_to_result<2 * kMaxN>(lds, T, 2 * n * n, threadIdx.x / n, 2 * n * b, 2 * n, acc,
-                                   red.partial, red.counter, red.result);
+                                   red.partial, red.counter, red.result, blockIdx.x, gridDim.x);
 }
 
 // X_b += sum_a P_a al_ab ; R_b -= sum_a Q_a al_ab   (al: n x n complex, row-major)
@@ -75,8 +75,8 @@ __global__ void __launch_bounds__(256) block_axpy_kernel(void *X, const void *P,
                                                          const void *Q, const double *al, int S,
                                                          int n) {
     using TX = typename SpinorT<FX>::real;
-    const SpinorBlock<FX> vx(X, S, n), vr(R, S, n);
-    const SpinorBlock<FP> vp(P, S, n), vq(Q, S, n);
+    const SpinorBlock<FX, true> vx(X, S, n), vr(R, S, n);
+    const SpinorBlock<FP, true> vp(P, S, n), vq(Q, S, n);
     const uint32_t total = (uint32_t)S * n;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += gridDim.x * blockDim.x) {
@@ -105,8 +105,8 @@ template <SpinorFmt FR, SpinorFmt FP>
 __global__ void __launch_bounds__(256) block_xpay_kernel(void *Pn, const void *R, const void *P,
                                                          const double *be, int S, int n) {
     using TP = typename SpinorT<FP>::real;
-    const SpinorBlock<FR> vr(R, S, n);
-    const SpinorBlock<FP> vp(P, S, n), vo(Pn, S, n);
+    const SpinorBlock<FR, true> vr(R, S, n);
+    const SpinorBlock<FP, true> vp(P, S, n), vo(Pn, S, n);
     const uint32_t total = (uint32_t)S * n;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += gridDim.x * blockDim.x) {

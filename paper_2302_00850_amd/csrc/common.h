@@ -80,8 +80,10 @@ struct HopArgs {
     double *partial;     // per-block partial sums [grid][R]
     unsigned *counter;   // last-block ticket, left at 0
     double *result;      // [R]
-    uint32_t total;      // Vh * groups threads of work
+    uint32_t total;      // (Lt / tchunk) * (Vh / Lt) * groups lanes of work
     int sites_per_block; // T: threads per block = T * groups
+    int tchunk;          // timeslices one lane walks (t-streaming); divides Lt
+    FastDiv div_ncol;    // division by the checkerboard sites of one timeslice
 };
 
 // Link chunk counts per format.

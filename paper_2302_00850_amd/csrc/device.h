@@ -155,6 +155,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void *base, uint32_t
                                              0x00020000);
 }
 
+// Same for a base known to be uniform across the wavefront: the empty asm makes it
+// opaque at each use, so the descriptor is rebuilt next to its loads on the scalar
+// unit instead of being hoisted out of the site loop together with dozens of
+// others (which overflows the SGPRs).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_u(const void *base, uint32_t bytes) {
+    const void *b = base;
+    asm volatile("" : "+s"(b));
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(b), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
 template <typename E>
 __device__ __forceinline__ E bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     E v;
@@ -193,8 +204,9 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, c
     }
 }
 
-// View of one parity block of a packed spinor field.
-template <SpinorFmt F>
+// View of one parity block of a packed spinor field.  UNI: the block base is the
+// same for every lane of a wavefront (true in the hop kernels).
+template <SpinorFmt F, bool UNI = false>
 struct SpinorBlock {
     using E = typename SpinorT<F>::elem;
     using R = typename SpinorT<F>::real;
@@ -209,7 +221,12 @@ struct SpinorBlock {
     }
 
     __device__ __forceinline__ __amdgpu_buffer_rsrc_t comp(int c) const {
+        if constexpr (UNI) return buf_u(data + (size_t)c * SR, SR * (uint32_t)sizeof(E));
         return buf(data + (size_t)c * SR, SR * (uint32_t)sizeof(E));
+    }
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t nrm() const {
+        if constexpr (UNI) return buf_u(norm, SR * 4u);
+        return buf(norm, SR * 4u);
     }
 
     // the 12 components of site i, rhs r, in compute precision
@@ -228,7 +245,7 @@ struct SpinorBlock {
         const uint32_t e = i * nrhs + r;
         const uint32_t off = e * (uint32_t)sizeof(E);
         if constexpr (F == SpinorFmt::F16) {
-            *scale = bload<float>(buf(norm, SR * 4u), e * 4u);
+            *scale = bload<float>(nrm(), e * 4u);
         } else {
             *scale = (R)1;
         }
@@ -237,6 +254,18 @@ struct SpinorBlock {
             const E h = bload<E>(comp(c), off);
             v[c] = {(R)h.x, (R)h.y};
         }
+    }
+
+    // FP16 only: the raw packed halves of site i, rhs r and the site scale.
+    template <typename H2>
+    __device__ __forceinline__ void load_raw_h2(uint32_t i, uint32_t r, H2 v[12],
+                                                float *scale) const {
+        static_assert(F == SpinorFmt::F16, "packed halves exist for FP16 blocks only");
+        const uint32_t e = i * nrhs + r;
+        const uint32_t off = e * (uint32_t)sizeof(E);
+        *scale = bload<float>(nrm(), e * 4u);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = bload<H2>(comp(c), off);
     }
 
     // Store; v is replaced by the values actually stored (FP16 rounding).
@@ -259,7 +288,7 @@ struct SpinorBlock {
                 bstore<E>(comp(c), off, h);
                 v[c] = {m * (float)h.x, m * (float)h.y};
             }
-            bstore<float>(buf(norm, SR * 4u), e * 4u, m);
+            bstore<float>(nrm(), e * 4u, m);
         } else {
 #pragma unroll
             for (int c = 0; c < 12; ++c) bstore<E>(comp(c), off, E{v[c].x, v[c].y});
@@ -294,30 +323,35 @@ struct LinkT<LinkFmt::F16_12> {
 
 // Load U_mu at checkerboard site i of parity p; row 2 rebuilt as conj(row0 x row1)
 // for the 12-real formats.
-template <LinkFmt F, typename T>
+// UNI: parity p is the same for every lane of the wavefront.
+template <LinkFmt F, typename T, bool UNI = true>
 __device__ __forceinline__ void load_link(const void *gauge, int S, int p, int mu, uint32_t i,
                                           cpx<T> u[3][3]) {
     using CH = typename LinkT<F>::chunk;
+    const auto buf_u = [](const void *b, uint32_t n) {
+        if constexpr (UNI) return ::cola::buf_u(b, n);
+        return ::cola::buf(b, n);
+    };
     constexpr int N = link_chunks(F);
     const CH *base = (const CH *)gauge + ((size_t)(p * 4 + mu) * N) * (size_t)S;  // uniform
     const uint32_t off = i * (uint32_t)sizeof(CH);
     if constexpr (F == LinkFmt::F64_18) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const CH c = bload<CH>(buf(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
+            const CH c = bload<CH>(buf_u(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
             u[k / 3][k % 3] = {(T)c.a, (T)c.b};
         }
         return;
     } else if constexpr (F == LinkFmt::F64_12) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const CH c = bload<CH>(buf(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
+            const CH c = bload<CH>(buf_u(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
             u[k / 3][k % 3] = {(T)c.a, (T)c.b};
         }
     } else {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const CH c = bload<CH>(buf(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
+            const CH c = bload<CH>(buf_u(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
             u[(2 * k) / 3][(2 * k) % 3] = {(T)c.a, (T)c.b};
             u[(2 * k + 1) / 3][(2 * k + 1) % 3] = {(T)c.c, (T)c.d};
         }
@@ -413,6 +447,91 @@ __device__ __forceinline__ void expand_add(int mu, T sg, const cpx<T> w[6], cpx<
     }
 }
 
+// ------------------------------------------------ FP16 packed path (dot2 products)
+
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+// a + s b and a + s i b on packed (re, im) halves; one v_pk_fma_f16 each
+__device__ __forceinline__ h2 add_s_h2(h2 a, _Float16 s, h2 b) { return a + h2{s, s} * b; }
+__device__ __forceinline__ h2 add_si_h2(h2 a, _Float16 s, h2 b) {
+    return a + h2{s, s} * h2{-b.y, b.x};
+}
+
+// Spin projection (1 + sg g_mu) of a spinor held as packed halves (same table as project).
+__device__ __forceinline__ void project_h2(int mu, _Float16 sg, const h2 p[12], h2 h[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const h2 p0 = p[c], p1 = p[3 + c], p2 = p[6 + c], p3 = p[9 + c];
+        switch (mu) {
+            case 0: h[c] = add_si_h2(p0, sg, p3); h[3 + c] = add_si_h2(p1, sg, p2); break;
+            case 1: h[c] = add_s_h2(p0, -sg, p3); h[3 + c] = add_s_h2(p1, sg, p2); break;
+            case 2: h[c] = add_si_h2(p0, sg, p2); h[3 + c] = add_si_h2(p1, -sg, p3); break;
+            default: h[c] = add_s_h2(p0, sg, p2); h[3 + c] = add_s_h2(p1, sg, p3); break;
+        }
+    }
+}
+
+// FP16 12-real link as packed halves; row 2 = conj(row0 x row1) computed in FP32 and
+// rounded to FP16.
+__device__ __forceinline__ void load_link_h2(const void *gauge, int S, int p, int mu, uint32_t i,
+                                             h2 u[3][3]) {
+    using CH = LinkT<LinkFmt::F16_12>::chunk;
+    const CH *base = (const CH *)gauge + ((size_t)(p * 4 + mu) * 3) * (size_t)S;
+    const uint32_t off = i * (uint32_t)sizeof(CH);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const CH c = bload<CH>(buf_u(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
+        u[(2 * k) / 3][(2 * k) % 3] = h2{c.a, c.b};
+        u[(2 * k + 1) / 3][(2 * k + 1) % 3] = h2{c.c, c.d};
+    }
+    cpx<float> a[3], b[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        a[k] = {(float)u[0][k].x, (float)u[0][k].y};
+        b[k] = {(float)u[1][k].x, (float)u[1][k].y};
+    }
+    const cpx<float> c0 = cmul(a[1], b[2]) - cmul(a[2], b[1]);
+    const cpx<float> c1 = cmul(a[2], b[0]) - cmul(a[0], b[2]);
+    const cpx<float> c2 = cmul(a[0], b[1]) - cmul(a[1], b[0]);
+    u[2][0] = h2{(_Float16)c0.x, (_Float16)(-c0.y)};
+    u[2][1] = h2{(_Float16)c1.x, (_Float16)(-c1.y)};
+    u[2][2] = h2{(_Float16)c2.x, (_Float16)(-c2.y)};
+}
+
+// Operands for w = V h with two dot2 per complex entry: w_a = sum_b (re: dot(A_ab, h_b),
+// im: dot(B_ab, h_b)).  Forward V = U: A = (u.x, -u.y), B = (u.y, u.x).
+// Backward V = U^H: A_ab = u_ba, B_ab = (-u_ba.y, u_ba.x).
+__device__ __forceinline__ void dot2_operands(const h2 u[3][3], bool dagger, h2 A[3][3],
+                                              h2 B[3][3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const h2 v = dagger ? u[b][a] : u[a][b];
+            if (dagger) {
+                A[a][b] = v;
+                B[a][b] = h2{-v.y, v.x};
+            } else {
+                A[a][b] = h2{v.x, -v.y};
+                B[a][b] = h2{v.y, v.x};
+            }
+        }
+}
+
+__device__ __forceinline__ void mul_dot2(const h2 A[3][3], const h2 B[3][3], const h2 h[3],
+                                         cpx<float> w[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float re = __builtin_amdgcn_fdot2(A[a][0], h[0], 0.f, false);
+        float im = __builtin_amdgcn_fdot2(B[a][0], h[0], 0.f, false);
+        re = __builtin_amdgcn_fdot2(A[a][1], h[1], re, false);
+        im = __builtin_amdgcn_fdot2(B[a][1], h[1], im, false);
+        re = __builtin_amdgcn_fdot2(A[a][2], h[2], re, false);
+        im = __builtin_amdgcn_fdot2(B[a][2], h[2], im, false);
+        w[a] = {re, im};
+    }
+}
+
 // ------------------------------------------------------------------ clover
 
 // out = C in, C = two Hermitian 6x6 chiral blocks (spins {0,1} and {2,3}).
@@ -429,13 +548,13 @@ __device__ __forceinline__ void clover_apply(const void *clov, int S, int p, uin
         cpx<T> o[15];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const pair v = bload<pair>(buf(q + (size_t)k * S, (uint32_t)S * sizeof(pair)), off);
+            const pair v = bload<pair>(buf_u(q + (size_t)k * S, (uint32_t)S * sizeof(pair)), off);
             d[2 * k] = (T)v.a;
             d[2 * k + 1] = (T)v.b;
         }
 #pragma unroll
         for (int k = 0; k < 15; ++k) {
-            const pair v = bload<pair>(buf(q + (size_t)(3 + k) * S, (uint32_t)S * sizeof(pair)), off);
+            const pair v = bload<pair>(buf_u(q + (size_t)(3 + k) * S, (uint32_t)S * sizeof(pair)), off);
             o[k] = {(T)v.a, (T)v.b};
         }
         const cpx<T> *v = in + 6 * blk;
@@ -464,7 +583,7 @@ __device__ __forceinline__ void clover_apply(const void *clov, int S, int p, uin
 template <int NV>
 __device__ void block_sum_to_result(double *red, int T, int width, int slot, int q0, int n,
                                     const double (&v)[NV], double *partial, unsigned *counter,
-                                    double *result) {
+                                    double *result, uint32_t bid, uint32_t nblocks) {
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
     for (int k = tid; k < T * width; k += nt) red[k] = 0.0;
@@ -477,18 +596,18 @@ __device__ void block_sum_to_result(double *red, int T, int width, int slot, int
         for (int k = tid; k < w * width; k += nt) red[k] += red[k + w * width];
         __syncthreads();
     }
-    for (int k = tid; k < width; k += nt) partial[(size_t)blockIdx.x * width + k] = red[k];
+    for (int k = tid; k < width; k += nt) partial[(size_t)bid * width + k] = red[k];
     __shared__ unsigned ticket;
     __threadfence();
     __syncthreads();
     if (tid == 0)
         ticket = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    if (ticket != gridDim.x - 1) return;
+    if (ticket != nblocks - 1) return;
     __threadfence();
     // last block: fixed-order sum over blocks, slot s handles blocks s, s+T, ...
     // (four independent partial sums so the loads overlap)
-    const int nb = gridDim.x;
+    const int nb = (int)nblocks;
     for (int k = tid; k < T * width; k += nt) {
         const int s = k / width, q = k - s * width;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;

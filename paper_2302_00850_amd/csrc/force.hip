@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) force_kernel(const Geom g, const void *ga
         }
         const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
         C u[3][3];
-        load_link<LinkFmt::F64_18, double>(gauge, g.S, p, mu, s >> 1, u);
+        load_link<LinkFmt::F64_18, double, false>(gauge, g.S, p, mu, s >> 1, u);
         // W = U G^H
         C W[9];
 #pragma unroll

@@ -21,7 +21,8 @@ constexpr int kReduceGrid = 2048;  // blocks of a launch that reduces
 struct TuneEntry {
     int rpt = 1;
     int sites_per_block = 64;
-    int grid = 0;  // 0: one block per sites_per_block sites
+    int grid = 0;    // 0: one block per sites_per_block site columns
+    int tchunk = 1;  // timeslices walked by one lane
     double ms = 0;
 };
 

@@ -33,9 +33,9 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     extern __shared__ double red[];
     const Geom &g = a.g;
     const int p = a.parity;
-    const SpinorBlock<SF> in(a.in, g.S, a.nrhs);
-    const SpinorBlock<SF> out(a.out, g.S, a.nrhs);
-    const SpinorBlock<SF> xin(a.x ? a.x : a.out, g.S, a.nrhs);
+    const SpinorBlock<SF, true> in(a.in, g.S, a.nrhs);
+    const SpinorBlock<SF, true> out(a.out, g.S, a.nrhs);
+    const SpinorBlock<SF, true> xin(a.x ? a.x : a.out, g.S, a.nrhs);
     const T sg_f = a.dagger ? (T)1 : (T)-1;
     const T sg_b = -sg_f;
     double nrm[RPT];
@@ -44,9 +44,15 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
 
     const uint32_t stride = gridDim.x * blockDim.x;
     const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-    for (uint32_t t = lb * blockDim.x + threadIdx.x; t < a.total; t += stride) {
-        const uint32_t i = fdiv(t, a.div_groups);
-        const uint32_t j = t - i * (uint32_t)a.groups;
+    const uint32_t ncol = (uint32_t)g.s3;  // checkerboard sites of one timeslice
+    // Lane w owns rhs group j of spatial column c in time chunk k and walks the chunk's
+    // timeslices: the spinors its t-neighbours need were fetched one step earlier.
+    for (uint32_t w = lb * blockDim.x + threadIdx.x; w < a.total; w += stride)
+    for (int tt = 0; tt < a.tchunk; ++tt) {
+        const uint32_t q = fdiv(w, a.div_groups);
+        const uint32_t j = w - q * (uint32_t)a.groups;
+        const uint32_t k = fdiv(q, a.div_ncol);
+        const uint32_t i = q + k * ncol * (uint32_t)(a.tchunk - 1) + (uint32_t)tt * ncol;
         int x[4];
         site_coords(g, i, p, x);
         C acc[RPT][12];
@@ -63,8 +69,6 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
                 // dir 1: (1 + sg_b g_mu) e- U_mu(x-mu)^H psi(x-mu)
                 const uint32_t n = dir == 0 ? nb_fwd(g, i, x, mu) : nb_bwd(g, i, x, mu);
                 const T sg = dir == 0 ? sg_f : sg_b;
-                C u[3][3];
-                load_link<LF, T>(a.gauge, g.S, dir == 0 ? p : 1 - p, mu, dir == 0 ? i : n, u);
                 const bool bnd = dir == 0 ? x[mu] == g.L[mu] - 1 : x[mu] == 0;
                 T eta = (T)1;
                 C ph = {(T)1, (T)0};
@@ -74,6 +78,30 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
                     const T im = dir == 0 ? (T)a.phase[mu].y : -(T)a.phase[mu].y;
                     ph = bnd ? C{(T)a.phase[mu].x, im} : C{(T)1, (T)0};
                 }
+                if constexpr (SF == SpinorFmt::F16) {
+                    // packed-half projection and dot2 products: FP16 x FP16 products are
+                    // exact and summed in FP32; the per-site scale rides on eta
+                    h2 uh[3][3], A[3][3], B[3][3];
+                    load_link_h2(a.gauge, g.S, dir == 0 ? p : 1 - p, mu, dir == 0 ? i : n, uh);
+                    dot2_operands(uh, dir == 1, A, B);
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        h2 s[12], hh[6];
+                        C w[6];
+                        float scl;
+                        in.load_raw_h2(n, j * RPT + r, s, &scl);
+                        project_h2(mu, (_Float16)sg, s, hh);
+                        mul_dot2(A, B, hh, w);
+                        mul_dot2(A, B, hh + 3, w + 3);
+                        if constexpr (!RPH) {
+#pragma unroll
+                            for (int k = 0; k < 6; ++k) w[k] = cmul(ph, w[k]);
+                        }
+                        expand_add(mu, sg, w, acc[r], eta * scl);
+                    }
+                } else {
+                C u[3][3];
+                load_link<LF, T>(a.gauge, g.S, dir == 0 ? p : 1 - p, mu, dir == 0 ? i : n, u);
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
                     C s[12], h[6], w[6];
@@ -93,6 +121,7 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
                     }
                     expand_add(mu, sg, w, acc[r], SF == SpinorFmt::F16 ? eta * scl : eta);
                 }
+                }  // non-FP16 path
                 // Register fence: the accumulators are final for this direction here, so
                 // the compiler cannot sink a direction's arithmetic to the end of the
                 // kernel (which kept every loaded spinor and link live at once).
@@ -145,7 +174,7 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
         const int slot = threadIdx.x / a.groups;
         const int jj = threadIdx.x - slot * a.groups;
         block_sum_to_result<RPT>(red, a.sites_per_block, a.nrhs, slot, jj * RPT, RPT, nrm,
-                                 a.partial, a.counter, a.result);
+                                 a.partial, a.counter, a.result, blockIdx.x, gridDim.x);
     }
 }
 

@@ -111,18 +111,29 @@ hipEvent_t take_event(cola_handle_t *h) {
     return e;
 }
 
-// Launch shape for one hop launch.
+// Launch shape for one hop launch: T site columns x groups lanes per block.
 void shape_for(const TuneEntry &t, int Vh, int nrhs, int *groups, int *T, int *grid, int *block) {
     *groups = nrhs / t.rpt;
     *T = t.sites_per_block;
     *block = *T * *groups;
-    long g = (Vh + *T - 1) / *T;
+    const long cols = Vh / t.tchunk;
+    long g = (cols + *T - 1) / *T;
     if (t.grid > 0 && t.grid < g) g = t.grid;
     if (g > kMaxGrid) g = kMaxGrid;
     *grid = (int)std::max(1L, g);
 }
 
-TuneEntry default_entry(int nrhs) {
+// Longest power-of-two time chunk (<= 16, dividing Lt) that still leaves about
+// 2^18 lanes of work, so a lattice fills the 256 CUs.
+int default_tchunk(const Geom &g, int groups) {
+    int tc = 1;
+    while (tc * 2 <= 16 && g.L[3] % (tc * 2) == 0 &&
+           (double)g.Vh * groups / (tc * 2) >= 262144.0)
+        tc *= 2;
+    return tc;
+}
+
+TuneEntry default_entry(const Geom &g, int nrhs) {
     TuneEntry t;
     t.rpt = 1;
     const int G = nrhs;
@@ -130,6 +141,7 @@ TuneEntry default_entry(int nrhs) {
     while (T * 2 * G <= 256) T *= 2;
     t.sites_per_block = T;
     t.grid = 0;
+    t.tchunk = default_tchunk(g, G);
     return t;
 }
 
@@ -159,8 +171,10 @@ int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, cons
     a.partial = h->partial;
     a.counter = h->counter;
     a.result = c.norm_result;
-    a.total = (uint32_t)h->g.Vh * (uint32_t)groups;
+    a.total = (uint32_t)(h->g.Vh / te.tchunk) * (uint32_t)groups;
     a.sites_per_block = T;
+    a.tchunk = te.tchunk;
+    a.div_ncol = make_fastdiv((uint32_t)h->g.s3);
     COLA_HIP(h, launch_hop(a, link_fmt(prec), te.rpt, grid, block, st));
     return COLA_OK;
 }
@@ -174,12 +188,16 @@ int tune_hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, TuneEntry *
         const int G = nrhs / rpt;
         for (int T : {4, 8, 16, 32, 64, 128, 256}) {
             if (T * G > 256 || T * G < 64) continue;
-            for (int grid : {0, 2048, 8192}) {
-                TuneEntry t;
-                t.rpt = rpt;
-                t.sites_per_block = T;
-                t.grid = grid;
-                cand.push_back(t);
+            for (int tc : {1, 2, 4, 8, 16}) {
+                if (h->g.L[3] % tc) continue;
+                for (int grid : {0, 2048}) {
+                    TuneEntry t;
+                    t.rpt = rpt;
+                    t.sites_per_block = T;
+                    t.grid = grid;
+                    t.tchunk = tc;
+                    cand.push_back(t);
+                }
             }
         }
     }
@@ -251,7 +269,7 @@ int hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, hipStream_t st) 
         COLA_TRY(tune_hop(h, c, prec, nrhs, &te, st));
         h->tune[key] = te;
     } else {
-        te = default_entry(nrhs);
+        te = default_entry(h->g, nrhs);
     }
     const bool timed = (h->flags & COLA_FLAG_TIMING) != 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
