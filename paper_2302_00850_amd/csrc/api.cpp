@@ -279,9 +279,10 @@ size_t cola_tune_dump(const cola_handle_t *h, char *buf, size_t len) {
         char e[256];
         snprintf(e, sizeof e,
                  "%s\"%s\": {\"rpt\": %d, \"sites_per_block\": %d, \"grid\": %d, "
-                 "\"tchunk\": %d, \"ms\": %.6f}",
+                 "\"tchunk\": %d, \"tile\": [%d, %d], \"ms\": %.6f}",
                  first ? "" : ", ", kv.first.c_str(), kv.second.rpt, kv.second.sites_per_block,
-                 kv.second.grid, kv.second.tchunk, kv.second.ms);
+                 kv.second.grid, kv.second.tchunk, kv.second.tile_y, kv.second.tile_z,
+                 kv.second.ms);
         s += e;
         first = false;
     }

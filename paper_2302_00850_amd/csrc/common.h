@@ -84,6 +84,10 @@ struct HopArgs {
     int sites_per_block; // T: threads per block = T * groups
     int tchunk;          // timeslices one lane walks (t-streaming); divides Lt
     FastDiv div_ncol;    // division by the checkerboard sites of one timeslice
+    // spatial tiling (tile_y > 0): work ordered (tile, t, column in tile); a tile is
+    // all x-rows of tile_y x tile_z (y, z) columns
+    int tile_y, tile_z;
+    FastDiv div_tcols, div_lt, div_lxh, div_ty, div_nty;
 };
 
 // Link chunk counts per format.

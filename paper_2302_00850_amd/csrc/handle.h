@@ -23,6 +23,8 @@ struct TuneEntry {
     int sites_per_block = 64;
     int grid = 0;    // 0: one block per sites_per_block site columns
     int tchunk = 1;  // timeslices walked by one lane
+    int tile_y = 0;  // spatial tile (all x-rows x tile_y x tile_z); 0 = lexicographic
+    int tile_z = 0;
     double ms = 0;
 };
 

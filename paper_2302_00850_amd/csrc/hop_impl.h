@@ -51,8 +51,25 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     for (int tt = 0; tt < a.tchunk; ++tt) {
         const uint32_t q = fdiv(w, a.div_groups);
         const uint32_t j = w - q * (uint32_t)a.groups;
-        const uint32_t k = fdiv(q, a.div_ncol);
-        const uint32_t i = q + k * ncol * (uint32_t)(a.tchunk - 1) + (uint32_t)tt * ncol;
+        uint32_t i;
+        if (a.tile_y > 0) {
+            // q = (tile * Lt + t) * tile_cols + col; col = xh + Lxh (yl + tile_y zl)
+            const uint32_t rest = fdiv(q, a.div_tcols);
+            const uint32_t col = q - rest * (uint32_t)(g.Lxh * a.tile_y * a.tile_z);
+            const uint32_t tile = fdiv(rest, a.div_lt);
+            const uint32_t t = rest - tile * (uint32_t)g.L[3];
+            const uint32_t r1 = fdiv(col, a.div_lxh);
+            const uint32_t xh = col - r1 * (uint32_t)g.Lxh;
+            const uint32_t zl = fdiv(r1, a.div_ty);
+            const uint32_t yl = r1 - zl * (uint32_t)a.tile_y;
+            const uint32_t tz = fdiv(tile, a.div_nty);
+            const uint32_t ty = tile - tz * (uint32_t)(g.L[1] / a.tile_y);
+            const uint32_t y = ty * a.tile_y + yl, z = tz * a.tile_z + zl;
+            i = xh + (uint32_t)g.Lxh * (y + (uint32_t)g.L[1] * z) + ncol * t;
+        } else {
+            const uint32_t k = fdiv(q, a.div_ncol);
+            i = q + k * ncol * (uint32_t)(a.tchunk - 1) + (uint32_t)tt * ncol;
+        }
         int x[4];
         site_coords(g, i, p, x);
         C acc[RPT][12];

@@ -133,6 +133,12 @@ int default_tchunk(const Geom &g, int groups) {
     return tc;
 }
 
+// A spatial tile must divide the y and z extents (tile_y = 0: no tiling).
+bool tile_ok(const Geom &g, int ty, int tz) {
+    if (ty == 0 && tz == 0) return true;
+    return ty > 0 && tz > 0 && g.L[1] % ty == 0 && g.L[2] % tz == 0;
+}
+
 TuneEntry default_entry(const Geom &g, int nrhs) {
     TuneEntry t;
     t.rpt = 1;
@@ -142,6 +148,19 @@ TuneEntry default_entry(const Geom &g, int nrhs) {
     t.sites_per_block = T;
     t.grid = 0;
     t.tchunk = default_tchunk(g, G);
+    // Measurement knob: COLA_HOP_SHAPE="rpt,sites_per_block,grid,tchunk" pins the
+    // untuned launch shape (ignored unless every field is valid for this launch).
+    if (const char *env = getenv("COLA_HOP_SHAPE")) {
+        TuneEntry e;
+        const int n = sscanf(env, "%d,%d,%d,%d,%d,%d", &e.rpt, &e.sites_per_block, &e.grid,
+                             &e.tchunk, &e.tile_y, &e.tile_z);
+        if ((n == 4 || n == 6) && (e.rpt == 1 || e.rpt == 2 || e.rpt == 4) && nrhs % e.rpt == 0 &&
+            e.sites_per_block >= 1 && (e.sites_per_block & (e.sites_per_block - 1)) == 0 &&
+            e.sites_per_block * (nrhs / e.rpt) <= 256 && e.grid >= 0 && e.tchunk >= 1 &&
+            g.L[3] % e.tchunk == 0 && tile_ok(g, e.tile_y, e.tile_z) &&
+            (e.tile_y == 0 || e.tchunk == 1))
+            t = e;
+    }
     return t;
 }
 
@@ -175,6 +194,16 @@ int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, cons
     a.sites_per_block = T;
     a.tchunk = te.tchunk;
     a.div_ncol = make_fastdiv((uint32_t)h->g.s3);
+    a.tile_y = te.tile_y;
+    a.tile_z = te.tile_z;
+    if (te.tile_y > 0) {
+        const Geom &g = h->g;
+        a.div_tcols = make_fastdiv((uint32_t)(g.Lxh * te.tile_y * te.tile_z));
+        a.div_lt = make_fastdiv((uint32_t)g.L[3]);
+        a.div_lxh = make_fastdiv((uint32_t)g.Lxh);
+        a.div_ty = make_fastdiv((uint32_t)te.tile_y);
+        a.div_nty = make_fastdiv((uint32_t)(g.L[1] / te.tile_y));
+    }
     COLA_HIP(h, launch_hop(a, link_fmt(prec), te.rpt, grid, block, st));
     return COLA_OK;
 }
@@ -198,6 +227,16 @@ int tune_hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, TuneEntry *
                     t.tchunk = tc;
                     cand.push_back(t);
                 }
+            }
+            const int tiles[][2] = {{4, 4}, {8, 4}, {4, 8}, {8, 8}, {16, 8}, {8, 16}, {16, 16}};
+            for (const auto &tl : tiles) {
+                if (!tile_ok(h->g, tl[0], tl[1])) continue;
+                TuneEntry t;
+                t.rpt = rpt;
+                t.sites_per_block = T;
+                t.tile_y = tl[0];
+                t.tile_z = tl[1];
+                cand.push_back(t);
             }
         }
     }

@@ -176,6 +176,39 @@ def test_dslash_argument_errors(fields):
         lat.dslash(buf, other, cola.COLA_OP_HOP, 0, 0, 17)     # too many rhs
 
 
+SHAPES = ["1,16,0,2", "1,16,0,5", "1,64,0,10", "1,16,0,1,2,2", "1,8,0,1,4,2", "1,32,3,1,4,4",
+          "2,16,0,2", "4,8,0,1,2,4"]
+
+
+@pytest.mark.parametrize("prec", [0, 2, 3])
+def test_hop_identical_across_launch_shapes(fields, prec, monkeypatch):
+    """Traversal order (time chunks, spatial tiles, XCD block order), rhs per lane and
+    grid size change only which lane computes a site: outputs are bitwise identical."""
+    U, psi = fields
+    nrhs = 4
+    lat = _lat(U, ANTI)
+    pin = lat.pack(_cuda(psi[:nrhs]), prec, 1)
+    ref = lat.empty_packed(prec, nrhs, 0)
+    monkeypatch.delenv("COLA_HOP_SHAPE", raising=False)
+    lat.dslash(ref, pin, cola.COLA_OP_HOP, 0, prec, nrhs)
+    for shape in SHAPES:
+        if prec == 0 and not shape.startswith("1,"):
+            continue  # FP64 keeps one rhs per lane
+        monkeypatch.setenv("COLA_HOP_SHAPE", shape)
+        out = lat.empty_packed(prec, nrhs, 0)
+        lat.dslash(out, pin, cola.COLA_OP_HOP, 0, prec, nrhs)
+        assert torch.equal(out, ref), shape
+    # and the fused-norm path agrees across shapes to rounding order
+    monkeypatch.setenv("COLA_HOP_SHAPE", "1,16,0,1,2,2")
+    a = lat.pack(_cuda(psi[:nrhs]), prec, 0)
+    out = lat.empty_packed(prec, nrhs, 0)
+    lat.dslash(out, a, cola.COLA_OP_SCHUR, 0, prec, nrhs)
+    monkeypatch.delenv("COLA_HOP_SHAPE")
+    out2 = lat.empty_packed(prec, nrhs, 0)
+    lat.dslash(out2, a, cola.COLA_OP_SCHUR, 0, prec, nrhs)
+    assert torch.equal(out, out2)
+
+
 def test_hop_deterministic_and_timing_stats(fields):
     U, psi = fields
     lat = _lat(U, ANTI, flags=cola.COLA_FLAG_TIMING)
