@@ -16,6 +16,7 @@ FP64 CPU oracle on the machine's host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,6 +32,38 @@ HBM_PEAK_GBS = 8000.0
 DIMS = (32, 32, 32, 64)
 KAPPA = 0.12
 TOL = 1e-10
+
+
+# rocprofv3 counter summary of the FP16 hop launches of this workload (HBM bytes per
+# launch); valid only for the hop sources it was taken with.
+COUNTERS = os.path.join(ROOT, "profiles", "hop_fp16_12rhs_32x32x32x64_solve_counters.txt")
+HOP_SOURCES = ["hop_impl.h", "device.h", "common.h", "hop_f16_12.hip", "ops.cpp"]
+
+
+def hop_sources_sha256():
+    h = hashlib.sha256()
+    for f in HOP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2302_00850_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per FP16 hop launch (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    same counter's reading for a plain copy of known size) from the committed
+    summary, or None when there is none or the hop sources changed since."""
+    try:
+        with open(COUNTERS) as fh:
+            kv = dict(l.split(":", 1) for l in fh.read().splitlines()
+                      if ":" in l and not l.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("sources_sha256", "").strip() != hop_sources_sha256():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -106,18 +139,131 @@ def hop_mode(args):
             torch.cuda.empty_cache()
 
 
+def workloads_mode(args):
+    """The other synthetic workloads, one JSON line each (time to a 1e-10 residual etc.)."""
+    import torch
+
+    from paper_2302_00850_amd import cola
+    from paper_2302_00850_amd.synth import Synth, bc_phases, point_sources
+
+    bc = bc_phases((0, 0, 0, np.pi))
+    sel = args.workloads.split(",")
+
+    def solve(lat, b, **kw):
+        lat.cg(b, **kw)  # warm (allocations, first launches)
+        lat.reset_stats()
+        torch.cuda.synchronize()
+        return lat.cg(b, **kw)
+
+    def hop_gbs(lat, prec):
+        st = lat.stats(prec)
+        return st["hop_bytes"] / st["hop_seconds"] / 1e9 if st["hop_seconds"] else None
+
+    if "mixed" in sel:
+        dims = (16, 16, 16, 32)
+        s = Synth(0, device="cuda")
+        U = s.gauge(dims)
+        b = s.gaussian_spinor(dims, 1)
+        lat = cola.Lattice(dims, KAPPA, bc, 0.0, cola.COLA_FLAG_TIMING)
+        lat.set_gauge(U)
+        _, i64 = solve(lat, b, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP64, tol=TOL)
+        g64 = hop_gbs(lat, cola.COLA_FP64)
+        _, i32 = solve(lat, b, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP32_RELIABLE,
+                    tol=TOL, reliable_interval=50)
+        g32 = hop_gbs(lat, cola.COLA_FP32)
+        print(json.dumps({"workload": "wilson_eo_16x16x16x32_fp32_reliable", "lattice": list(dims),
+                          "fp64": {"seconds": i64["seconds"], "iterations": i64["iterations"],
+                                   "residual": i64["true_rel_residual"][0], "hop_GBs": g64},
+                          "fp32_reliable": {"seconds": i32["seconds"],
+                                            "iterations": i32["iterations"],
+                                            "reliable_updates": i32["reliable_updates"],
+                                            "residual": i32["true_rel_residual"][0],
+                                            "hop_GBs": g32},
+                          "speedup": i64["seconds"] / i32["seconds"],
+                          "note": "working set below the 256 MB infinity cache"}), flush=True)
+        lat.close()
+    if "force" in sel:
+        dims = (24, 24, 24, 48)
+        s = Synth(0, device="cuda")
+        U = s.gauge(dims)
+        eta = s.gaussian_spinor(dims, 1)
+        lat = cola.Lattice(dims, KAPPA, bc, 0.0, cola.COLA_FLAG_TIMING)
+        lat.set_gauge(U)
+        ep = lat.pack(eta, cola.COLA_FP64, -1)
+        pp = lat.empty_packed(cola.COLA_FP64, 1, -1)
+        lat.dslash(pp, ep, cola.COLA_OP_MDAG, -1, cola.COLA_FP64, 1)
+        phi = lat.unpack(pp, cola.COLA_FP64, 1, -1)
+        X, info = solve(lat, phi, system=cola.COLA_SYS_MDAGM, scheme=cola.COLA_CG_FP64,
+                        tol=1e-12)
+        Xp = lat.pack(X, cola.COLA_FP64, -1)
+        Yp = lat.empty_packed(cola.COLA_FP64, 1, -1)
+        lat.dslash(Yp, Xp, cola.COLA_OP_M, -1, cola.COLA_FP64, 1)
+        Y = lat.unpack(Yp, cola.COLA_FP64, 1, -1)
+        lat.force(X[0], Y[0])
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(5):
+            lat.force(X[0], Y[0], cola.COLA_FORCE_LIE)
+        ev1.record()
+        torch.cuda.synchronize()
+        fms = ev0.elapsed_time(ev1) / 5
+        V = int(np.prod(dims))
+        # X, Y at two sites per link read (cache-shared), links 144 B, force 144 B out
+        fbytes = V * (2 * 192 + 4 * 144 + 4 * 144)
+        print(json.dumps({"workload": "force_24x24x24x48", "lattice": list(dims),
+                          "solve_seconds": info["seconds"], "iterations": info["iterations"],
+                          "force_ms": fms, "force_GBs": fbytes / fms / 1e6}), flush=True)
+        lat.close()
+    if "clover" in sel:
+        dims = (48, 48, 48, 96)
+        s = Synth(0, device="cuda", rng="torch")
+        U = s.gauge(dims)
+        b = point_sources(dims, device="cuda")
+        lat = cola.Lattice(dims, 0.118, bc, 1.0, cola.COLA_FLAG_TIMING)
+        lat.set_gauge(U)
+        _, i32 = solve(lat, b, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP32_DEFECT, tol=TOL,
+                    block=args.block)
+        g32 = hop_gbs(lat, cola.COLA_FP32)
+        b1 = b[:1].clone()
+        _, i64 = solve(lat, b1, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP64, tol=TOL)
+        g64 = hop_gbs(lat, cola.COLA_FP64)
+        print(json.dumps({"workload": "clover_eo_48x48x48x96_12rhs_fp32defect",
+                          "lattice": list(dims), "block_cg": bool(args.block),
+                          "mixed_12rhs": {"seconds": i32["seconds"],
+                                          "per_source": i32["seconds"] / 12,
+                                          "iterations": i32["iterations"],
+                                          "outer_cycles": i32["outer_cycles"],
+                                          "max_residual": max(i32["true_rel_residual"]),
+                                          "hop_GBs": g32},
+                          "fp64_1rhs": {"seconds": i64["seconds"],
+                                        "iterations": i64["iterations"],
+                                        "residual": i64["true_rel_residual"][0], "hop_GBs": g64},
+                          "speedup_per_source": i64["seconds"] / (i32["seconds"] / 12)}),
+              flush=True)
+        lat.close()
+
+
 def copy_mode(args):
-    """A plain device-to-device copy of known size (HBM counter calibration)."""
+    """A plain device-to-device copy of known size: HBM counter calibration and the
+    achievable copy bandwidth (bytes read + written per second)."""
     import torch
 
     n = 1 << 30
     src = torch.ones(n, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
     for _ in range(args.iters):
         dst.copy_(src)
+    ev1.record()
     torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.iters
     print(json.dumps({"mode": "copy", "bytes_read": n, "bytes_written": n,
-                      "copies": args.iters}), flush=True)
+                      "copies": args.iters + 1, "avg_ms": ms,
+                      "GBs": 2 * n / ms / 1e6}), flush=True)
 
 
 def main():
@@ -127,7 +273,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
-    ap.add_argument("--mode", default="solve", choices=["solve", "hop", "copy"])
+    ap.add_argument("--mode", default="solve", choices=["solve", "hop", "copy", "workloads"])
+    ap.add_argument("--workloads", default="mixed,force,clover",
+                    help="workloads mode: any of mixed, force, clover")
+    ap.add_argument("--block", type=int, default=0, help="use block CG in the multi-RHS solves")
     ap.add_argument("--lattice", default="32,32,32,64", help="hop mode: Lx,Ly,Lz,Lt")
     ap.add_argument("--prec", default="0,2,3", help="hop mode: precisions (0 FP64 .. 3 FP16)")
     ap.add_argument("--nrhs", default="1,12", help="hop mode: right-hand-side counts")
@@ -143,6 +292,9 @@ def main():
         return
     if args.mode == "copy":
         copy_mode(args)
+        return
+    if args.mode == "workloads":
+        workloads_mode(args)
         return
 
     import torch
@@ -226,7 +378,8 @@ def main():
                    "solver": "lockstep 12-RHS CG, FP16 storage + FP64 defect correction",
                    "tol": TOL, "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(), "hop_sources_sha256": hop_sources_sha256(),
                      "kernel": "hop_kernel FP16 12-real links, 12 rhs",
                      "bytes_per_launch": st16["hop_bytes"] / max(1, st16["hop_launches"]),
                      "avg_launch_ms": round(per_launch_ms, 4),

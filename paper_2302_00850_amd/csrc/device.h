@@ -122,6 +122,18 @@ struct alignas(4) half2s {
     _Float16 x, y;
 };
 
+// FP32 -> FP16 (round to nearest even) of two already-rounded FP32 values.  The
+// empty asm keeps the compiler from fusing the caller's scaling multiply into a
+// mixed-precision conversion (one rounding instead of two) in some instances and not
+// in others, which would make the stored halves depend on the launch shape.
+__device__ __forceinline__ half2s to_half2(float x, float y) {
+    asm volatile("" : "+v"(x), "+v"(y));
+    half2s h;
+    h.x = (_Float16)x;
+    h.y = (_Float16)y;
+    return h;
+}
+
 template <SpinorFmt F>
 struct SpinorT;
 template <>
@@ -148,6 +160,7 @@ struct SpinorT<SpinorFmt::F16> {
 // and drop stores.  Arrays handed to one descriptor are below 2^31 bytes
 // (checked on the host).
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x3_t __attribute__((ext_vector_type(3)));
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void *base, uint32_t bytes) {
@@ -178,6 +191,9 @@ __device__ __forceinline__ E bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     } else if constexpr (sizeof(E) == 8) {
         const u32x2_t w = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
         __builtin_memcpy(&v, &w, 8);
+    } else if constexpr (sizeof(E) == 12) {
+        const u32x3_t w = __builtin_amdgcn_raw_buffer_load_b96(r, (int)off, 0, 0);
+        __builtin_memcpy(&v, &w, 12);
     } else {
         static_assert(sizeof(E) == 16, "16-byte element");
         const u32x4_t w = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
@@ -196,6 +212,10 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, c
         u32x2_t w;
         __builtin_memcpy(&w, &v, 8);
         __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)off, 0, 0);
+    } else if constexpr (sizeof(E) == 12) {
+        u32x3_t w;
+        __builtin_memcpy(&w, &v, 12);
+        __builtin_amdgcn_raw_buffer_store_b96(w, r, (int)off, 0, 0);
     } else {
         static_assert(sizeof(E) == 16, "16-byte element");
         u32x4_t w;
@@ -268,6 +288,57 @@ struct SpinorBlock {
         for (int c = 0; c < 12; ++c) v[c] = bload<H2>(comp(c), off);
     }
 
+    // FP16 only: raw halves and site scales of the N consecutive right-hand sides
+    // r0 .. r0+N-1 of site i (r0 and the block's rhs count multiples of N), one
+    // N x 4-byte load per component.
+    template <int N, typename H2>
+    __device__ __forceinline__ void load_raw_h2_group(uint32_t i, uint32_t r0, H2 v[N][12],
+                                                      float scale[N]) const {
+        static_assert(F == SpinorFmt::F16, "packed halves exist for FP16 blocks only");
+        struct G { H2 x[N]; };
+        struct FS { float x[N]; };
+        const uint32_t off = (i * nrhs + r0) * 4u;
+        const FS f = bload<FS>(nrm(), off);
+#pragma unroll
+        for (int r = 0; r < N; ++r) scale[r] = f.x[r];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const G w = bload<G>(comp(c), off);
+#pragma unroll
+            for (int r = 0; r < N; ++r) v[r][c] = w.x[r];
+        }
+    }
+
+    // FP16 only: store N consecutive right-hand sides of site i (as load_raw_h2_group);
+    // v is replaced by the values actually stored.
+    template <int N>
+    __device__ __forceinline__ void store_group(uint32_t i, uint32_t r0, cpx<float> v[N][12]) const {
+        static_assert(F == SpinorFmt::F16, "grouped stores are for FP16 blocks");
+        struct G { half2s x[N]; };
+        struct FS { float x[N]; };
+        const uint32_t off = (i * nrhs + r0) * 4u;
+        G w[12];
+        FS f;
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            float m = 0.f;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[r][c].x), fabsf(v[r][c].y)));
+            if (!(m >= 1e-30f) && m == m) m = 0.f;  // as in store()
+            const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const half2s h = to_half2(v[r][c].x * inv, v[r][c].y * inv);
+                w[c].x[r] = h;
+                v[r][c] = {m * (float)h.x, m * (float)h.y};
+            }
+            f.x[r] = m;
+        }
+#pragma unroll
+        for (int c = 0; c < 12; ++c) bstore<G>(comp(c), off, w[c]);
+        bstore<FS>(nrm(), off, f);
+    }
+
     // Store; v is replaced by the values actually stored (FP16 rounding).
     __device__ __forceinline__ void store(uint32_t i, uint32_t r, cpx<R> v[12]) const {
         const uint32_t e = i * nrhs + r;
@@ -282,9 +353,7 @@ struct SpinorBlock {
             const float inv = m > 0.f ? 1.0f / m : 0.f;
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                half2s h;
-                h.x = (_Float16)(v[c].x * inv);
-                h.y = (_Float16)(v[c].y * inv);
+                const half2s h = to_half2(v[c].x * inv, v[c].y * inv);
                 bstore<E>(comp(c), off, h);
                 v[c] = {m * (float)h.x, m * (float)h.y};
             }
@@ -471,63 +540,90 @@ __device__ __forceinline__ void project_h2(int mu, _Float16 sg, const h2 p[12], 
     }
 }
 
-// FP16 12-real link as packed halves; row 2 = conj(row0 x row1) computed in FP32 and
-// rounded to FP16.
+// FP16 link prepared as dot2 operand pairs (one v_dot2 per real output term: the
+// FP16 x FP16 products are exact and summed in FP32).  For w = V h:
+//   V = U:   re = sum dot(A_ab, h_b) with A = (u.x, -u.y);  im: B = (u.y, u.x)
+//   V = U^H: A_ab = u_ba;                                   B_ab = (-u_ba.y, u_ba.x)
+struct LinkH2 {
+    h2 A[3][3];
+    h2 B[3][3];
+};
+
+__device__ __forceinline__ float dot2(h2 a, h2 b, float c) {
+    return __builtin_amdgcn_fdot2(a, b, c, false);
+}
+
+// Rows 0 and 1 of L.u given: row 2 = conj(row0 x row1) from dot2 products of the stored
+// halves, rounded once to FP16.  With a = row 0, b = row 1 and (k, k1, k2) cyclic,
+//   re row2_k =  Re(a_k1 b_k2) - Re(a_k2 b_k1) = dot(a_k1, (b.x, -b.y)_k2) + dot(a_k2, (-b.x, b.y)_k1)
+//   im row2_k = -Im(a_k1 b_k2) + Im(a_k2 b_k1) = dot(a_k1, (-b.y, -b.x)_k2) + dot(a_k2, (b.y, b.x)_k1)
+__device__ __forceinline__ void link_h2_row2(h2 u[3][3]) {
+    h2 bc[3], bn[3], bs[3], bsn[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const h2 v = u[1][k];
+        bc[k] = h2{v.x, -v.y};
+        bn[k] = h2{-v.x, v.y};
+        bs[k] = h2{v.y, v.x};
+        bsn[k] = h2{-v.y, -v.x};
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+        const float re = dot2(u[0][k2], bn[k1], dot2(u[0][k1], bc[k2], 0.f));
+        const float im = dot2(u[0][k2], bs[k1], dot2(u[0][k1], bsn[k2], 0.f));
+        u[2][k] = h2{(_Float16)re, (_Float16)im};
+    }
+}
+
+// The dot2 operands of V = U (DAG false) or V = U^H (DAG true) from the full link u.
+template <bool DAG>
+__device__ __forceinline__ void link_h2_prepare(const h2 u[3][3], LinkH2 &L) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if constexpr (DAG) {
+                const h2 v = u[b][a];
+                L.A[a][b] = v;
+                L.B[a][b] = h2{-v.y, v.x};
+            } else {
+                const h2 v = u[a][b];
+                L.A[a][b] = h2{v.x, -v.y};
+                L.B[a][b] = h2{v.y, v.x};
+            }
+        }
+}
+
+// Load U_mu at checkerboard site i of parity p (rows 0 and 1 stored, row 2 rebuilt) as
+// the dot2 operands of V = U (DAG false) or V = U^H (DAG true).
+template <bool DAG>
 __device__ __forceinline__ void load_link_h2(const void *gauge, int S, int p, int mu, uint32_t i,
-                                             h2 u[3][3]) {
+                                             LinkH2 &L) {
     using CH = LinkT<LinkFmt::F16_12>::chunk;
     const CH *base = (const CH *)gauge + ((size_t)(p * 4 + mu) * 3) * (size_t)S;
     const uint32_t off = i * (uint32_t)sizeof(CH);
+    h2 u[3][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const CH c = bload<CH>(buf_u(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
         u[(2 * k) / 3][(2 * k) % 3] = h2{c.a, c.b};
         u[(2 * k + 1) / 3][(2 * k + 1) % 3] = h2{c.c, c.d};
     }
-    cpx<float> a[3], b[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        a[k] = {(float)u[0][k].x, (float)u[0][k].y};
-        b[k] = {(float)u[1][k].x, (float)u[1][k].y};
-    }
-    const cpx<float> c0 = cmul(a[1], b[2]) - cmul(a[2], b[1]);
-    const cpx<float> c1 = cmul(a[2], b[0]) - cmul(a[0], b[2]);
-    const cpx<float> c2 = cmul(a[0], b[1]) - cmul(a[1], b[0]);
-    u[2][0] = h2{(_Float16)c0.x, (_Float16)(-c0.y)};
-    u[2][1] = h2{(_Float16)c1.x, (_Float16)(-c1.y)};
-    u[2][2] = h2{(_Float16)c2.x, (_Float16)(-c2.y)};
+    link_h2_row2(u);
+    link_h2_prepare<DAG>(u, L);
 }
 
-// Operands for w = V h with two dot2 per complex entry: w_a = sum_b (re: dot(A_ab, h_b),
-// im: dot(B_ab, h_b)).  Forward V = U: A = (u.x, -u.y), B = (u.y, u.x).
-// Backward V = U^H: A_ab = u_ba, B_ab = (-u_ba.y, u_ba.x).
-__device__ __forceinline__ void dot2_operands(const h2 u[3][3], bool dagger, h2 A[3][3],
-                                              h2 B[3][3]) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const h2 v = dagger ? u[b][a] : u[a][b];
-            if (dagger) {
-                A[a][b] = v;
-                B[a][b] = h2{-v.y, v.x};
-            } else {
-                A[a][b] = h2{v.x, -v.y};
-                B[a][b] = h2{v.y, v.x};
-            }
-        }
-}
-
-__device__ __forceinline__ void mul_dot2(const h2 A[3][3], const h2 B[3][3], const h2 h[3],
-                                         cpx<float> w[3]) {
+// w = V h for one colour vector h (V as prepared in L): three dot2 per real output.
+__device__ __forceinline__ void mul_h2(const LinkH2 &L, const h2 h[3], cpx<float> w[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        float re = __builtin_amdgcn_fdot2(A[a][0], h[0], 0.f, false);
-        float im = __builtin_amdgcn_fdot2(B[a][0], h[0], 0.f, false);
-        re = __builtin_amdgcn_fdot2(A[a][1], h[1], re, false);
-        im = __builtin_amdgcn_fdot2(B[a][1], h[1], im, false);
-        re = __builtin_amdgcn_fdot2(A[a][2], h[2], re, false);
-        im = __builtin_amdgcn_fdot2(B[a][2], h[2], im, false);
+        float re = dot2(L.A[a][0], h[0], 0.f);
+        float im = dot2(L.B[a][0], h[0], 0.f);
+        re = dot2(L.A[a][1], h[1], re);
+        im = dot2(L.B[a][1], h[1], im);
+        re = dot2(L.A[a][2], h[2], re);
+        im = dot2(L.B[a][2], h[2], im);
         w[a] = {re, im};
     }
 }

@@ -26,6 +26,88 @@
 
 namespace cola {
 
+// One of the eight hopping directions (MU, DIR) added into the accumulators of the
+// lane's RPT right-hand sides at checkerboard site i (coordinates x).  A template, so
+// the eight directions are unrolled by construction and every spin-projection branch
+// resolves at compile time.
+template <int MU, int DIR, SpinorFmt SF, LinkFmt LF, int RPT, bool RPH>
+__device__ __forceinline__ void hop_dir(const HopArgs &a, const SpinorBlock<SF, true> &in, int p,
+                                        uint32_t i, const int x[4], uint32_t j,
+                                        typename SpinorT<SF>::real sg_f,
+                                        cpx<typename SpinorT<SF>::real> acc[RPT][12]) {
+    using T = typename SpinorT<SF>::real;
+    using C = cpx<T>;
+    const Geom &g = a.g;
+    constexpr int mu = MU, dir = DIR;
+    const T sg_b = -sg_f;
+    // dir 0: (1 + sg_f g_mu) e+ U_mu(x) psi(x+mu)
+    // dir 1: (1 + sg_b g_mu) e- U_mu(x-mu)^H psi(x-mu)
+    const uint32_t n = dir == 0 ? nb_fwd(g, i, x, mu) : nb_bwd(g, i, x, mu);
+    const T sg = dir == 0 ? sg_f : sg_b;
+    const bool bnd = dir == 0 ? x[mu] == g.L[mu] - 1 : x[mu] == 0;
+    T eta = (T)1;
+    C ph = {(T)1, (T)0};
+    if constexpr (RPH) {
+        eta = bnd ? (T)a.phase[mu].x : (T)1;
+    } else {
+        const T im = dir == 0 ? (T)a.phase[mu].y : -(T)a.phase[mu].y;
+        ph = bnd ? C{(T)a.phase[mu].x, im} : C{(T)1, (T)0};
+    }
+    if constexpr (SF == SpinorFmt::F16) {
+        // packed-half projection and dot2 products: FP16 x FP16 products are exact
+        // and summed in FP32; the per-site scale rides on eta.  The link operands are
+        // prepared once for the lane's RPT right-hand sides, which are adjacent in
+        // memory: one wide load per component.
+        LinkH2 L;
+        load_link_h2<dir == 1>(a.gauge, g.S, dir == 0 ? p : 1 - p, mu, dir == 0 ? i : n, L);
+        h2 s[RPT][12];
+        float scl[RPT];
+        in.template load_raw_h2_group<RPT>(n, j * RPT, s, scl);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            h2 hh[6];
+            C w[6];
+            project_h2(mu, (_Float16)sg, s[r], hh);
+            mul_h2(L, hh, w);
+            mul_h2(L, hh + 3, w + 3);
+            if constexpr (!RPH) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) w[k] = cmul(ph, w[k]);
+            }
+            expand_add(mu, sg, w, acc[r], eta * scl[r]);
+        }
+    } else {
+        C u[3][3];
+        load_link<LF, T>(a.gauge, g.S, dir == 0 ? p : 1 - p, mu, dir == 0 ? i : n, u);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            C s[12], h[6], w[6];
+            T one;  // the site scale, 1 for FP32 and FP64 blocks
+            in.load_unscaled(n, j * RPT + r, s, &one);
+            project(mu, sg, s, h);
+            if constexpr (dir == 0) {
+                su3_mul(u, h, w);
+                su3_mul(u, h + 3, w + 3);
+            } else {
+                su3_dag_mul(u, h, w);
+                su3_dag_mul(u, h + 3, w + 3);
+            }
+            if constexpr (!RPH) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) w[k] = cmul(ph, w[k]);
+            }
+            expand_add(mu, sg, w, acc[r], eta);
+        }
+    }
+    // Register fence: the accumulators are final for this direction here, so the
+    // compiler cannot sink a direction's arithmetic to the end of the kernel (which
+    // kept every loaded spinor and link live at once).
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+#pragma unroll
+        for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(acc[r][c].x), "+v"(acc[r][c].y));
+}
+
 template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, int EPI, bool RPH>
 __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     using T = typename SpinorT<SF>::real;
@@ -37,7 +119,6 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     const SpinorBlock<SF, true> out(a.out, g.S, a.nrhs);
     const SpinorBlock<SF, true> xin(a.x ? a.x : a.out, g.S, a.nrhs);
     const T sg_f = a.dagger ? (T)1 : (T)-1;
-    const T sg_b = -sg_f;
     double nrm[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) nrm[r] = 0.0;
@@ -78,111 +159,54 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) acc[r][c] = {(T)0, (T)0};
 
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-#pragma unroll
-            for (int dir = 0; dir < 2; ++dir) {
-                // dir 0: (1 + sg_f g_mu) e+ U_mu(x) psi(x+mu)
-                // dir 1: (1 + sg_b g_mu) e- U_mu(x-mu)^H psi(x-mu)
-                const uint32_t n = dir == 0 ? nb_fwd(g, i, x, mu) : nb_bwd(g, i, x, mu);
-                const T sg = dir == 0 ? sg_f : sg_b;
-                const bool bnd = dir == 0 ? x[mu] == g.L[mu] - 1 : x[mu] == 0;
-                T eta = (T)1;
-                C ph = {(T)1, (T)0};
-                if constexpr (RPH) {
-                    eta = bnd ? (T)a.phase[mu].x : (T)1;
-                } else {
-                    const T im = dir == 0 ? (T)a.phase[mu].y : -(T)a.phase[mu].y;
-                    ph = bnd ? C{(T)a.phase[mu].x, im} : C{(T)1, (T)0};
-                }
-                if constexpr (SF == SpinorFmt::F16) {
-                    // packed-half projection and dot2 products: FP16 x FP16 products are
-                    // exact and summed in FP32; the per-site scale rides on eta
-                    h2 uh[3][3], A[3][3], B[3][3];
-                    load_link_h2(a.gauge, g.S, dir == 0 ? p : 1 - p, mu, dir == 0 ? i : n, uh);
-                    dot2_operands(uh, dir == 1, A, B);
-#pragma unroll
-                    for (int r = 0; r < RPT; ++r) {
-                        h2 s[12], hh[6];
-                        C w[6];
-                        float scl;
-                        in.load_raw_h2(n, j * RPT + r, s, &scl);
-                        project_h2(mu, (_Float16)sg, s, hh);
-                        mul_dot2(A, B, hh, w);
-                        mul_dot2(A, B, hh + 3, w + 3);
-                        if constexpr (!RPH) {
-#pragma unroll
-                            for (int k = 0; k < 6; ++k) w[k] = cmul(ph, w[k]);
-                        }
-                        expand_add(mu, sg, w, acc[r], eta * scl);
-                    }
-                } else {
-                C u[3][3];
-                load_link<LF, T>(a.gauge, g.S, dir == 0 ? p : 1 - p, mu, dir == 0 ? i : n, u);
-#pragma unroll
-                for (int r = 0; r < RPT; ++r) {
-                    C s[12], h[6], w[6];
-                    T scl;  // FP16 site scale, applied with the phase after the multiply
-                    in.load_unscaled(n, j * RPT + r, s, &scl);
-                    project(mu, sg, s, h);
-                    if (dir == 0) {
-                        su3_mul(u, h, w);
-                        su3_mul(u, h + 3, w + 3);
-                    } else {
-                        su3_dag_mul(u, h, w);
-                        su3_dag_mul(u, h + 3, w + 3);
-                    }
-                    if constexpr (!RPH) {
-#pragma unroll
-                        for (int k = 0; k < 6; ++k) w[k] = cmul(ph, w[k]);
-                    }
-                    expand_add(mu, sg, w, acc[r], SF == SpinorFmt::F16 ? eta * scl : eta);
-                }
-                }  // non-FP16 path
-                // Register fence: the accumulators are final for this direction here, so
-                // the compiler cannot sink a direction's arithmetic to the end of the
-                // kernel (which kept every loaded spinor and link live at once).
-#pragma unroll
-                for (int r = 0; r < RPT; ++r)
-#pragma unroll
-                    for (int c = 0; c < 12; ++c)
-                        asm volatile("" : "+v"(acc[r][c].x), "+v"(acc[r][c].y));
-            }
-        }
+        hop_dir<0, 0, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
+        hop_dir<0, 1, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
+        hop_dir<1, 0, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
+        hop_dir<1, 1, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
+        hop_dir<2, 0, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
+        hop_dir<2, 1, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
+        hop_dir<3, 0, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
+        hop_dir<3, 1, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
 
         const T ca = (T)a.a;
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const uint32_t rr = j * RPT + r;
-            C o[12];
-            if constexpr (EPI == EPI_NONE) {
-#pragma unroll
-                for (int c = 0; c < 12; ++c) o[c] = acc[r][c];
-            } else if constexpr (EPI == EPI_XPAY) {
+            C *o = acc[r];  // the epilogue result replaces the accumulator
+            if constexpr (EPI == EPI_XPAY) {
                 C xv[12];
                 xin.load(i, rr, xv);
 #pragma unroll
-                for (int c = 0; c < 12; ++c) o[c] = add_s(xv[c], ca, acc[r][c]);
+                for (int c = 0; c < 12; ++c) o[c] = add_s(xv[c], ca, o[c]);
             } else if constexpr (EPI == EPI_CLOV) {
-                clover_apply<CR, T>(a.clov, g.S, p, i, acc[r], o);
+                C d[12];
+#pragma unroll
+                for (int c = 0; c < 12; ++c) d[c] = o[c];
+                clover_apply<CR, T>(a.clov, g.S, p, i, d, o);
             } else if constexpr (EPI == EPI_CLOV_XPAY) {
                 C xv[12], cx[12];
                 xin.load(i, rr, xv);
                 clover_apply<CR, T>(a.clov, g.S, p, i, xv, cx);
 #pragma unroll
-                for (int c = 0; c < 12; ++c) o[c] = add_s(cx[c], ca, acc[r][c]);
-            } else {
+                for (int c = 0; c < 12; ++c) o[c] = add_s(cx[c], ca, o[c]);
+            } else if constexpr (EPI == EPI_XPAY_CLOV) {
                 C xv[12];
                 xin.load(i, rr, xv);
 #pragma unroll
-                for (int c = 0; c < 12; ++c) xv[c] = add_s(xv[c], ca, acc[r][c]);
+                for (int c = 0; c < 12; ++c) xv[c] = add_s(xv[c], ca, o[c]);
                 clover_apply<CR, T>(a.clov, g.S, p, i, xv, o);
             }
-            out.store(i, rr, o);  // o now holds the stored (rounded) values
-            if (a.want_norm) {
+            if constexpr (SF != SpinorFmt::F16) out.store(i, rr, o);
+        }
+        // FP16: one wide store per component for the lane's RPT right-hand sides;
+        // acc then holds the stored (rounded) values
+        if constexpr (SF == SpinorFmt::F16) out.template store_group<RPT>(i, j * RPT, acc);
+        if (a.want_norm) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
                 double s = 0.0;
 #pragma unroll
-                for (int c = 0; c < 12; ++c) s += (double)norm2(o[c]);
+                for (int c = 0; c < 12; ++c) s += (double)norm2(acc[r][c]);
                 nrm[r] += s;
             }
         }
@@ -225,12 +249,14 @@ hipError_t hop_launch_fmt(const HopArgs &a, int rpt, int grid, int block, hipStr
         if (rpt == 1) return hop_launch_epi<SF, LF, CR, 1, true>(a, grid, block, st);
         if constexpr (multi) {
             if (rpt == 2) return hop_launch_epi<SF, LF, CR, 2, true>(a, grid, block, st);
+            if (rpt == 3) return hop_launch_epi<SF, LF, CR, 3, true>(a, grid, block, st);
             if (rpt == 4) return hop_launch_epi<SF, LF, CR, 4, true>(a, grid, block, st);
         }
     } else {
         if (rpt == 1) return hop_launch_epi<SF, LF, CR, 1, false>(a, grid, block, st);
         if constexpr (multi) {
             if (rpt == 2) return hop_launch_epi<SF, LF, CR, 2, false>(a, grid, block, st);
+            if (rpt == 3) return hop_launch_epi<SF, LF, CR, 3, false>(a, grid, block, st);
             if (rpt == 4) return hop_launch_epi<SF, LF, CR, 4, false>(a, grid, block, st);
         }
     }

@@ -154,7 +154,7 @@ TuneEntry default_entry(const Geom &g, int nrhs) {
         TuneEntry e;
         const int n = sscanf(env, "%d,%d,%d,%d,%d,%d", &e.rpt, &e.sites_per_block, &e.grid,
                              &e.tchunk, &e.tile_y, &e.tile_z);
-        if ((n == 4 || n == 6) && (e.rpt == 1 || e.rpt == 2 || e.rpt == 4) && nrhs % e.rpt == 0 &&
+        if ((n == 4 || n == 6) && (e.rpt >= 1 && e.rpt <= 4) && nrhs % e.rpt == 0 &&
             e.sites_per_block >= 1 && (e.sites_per_block & (e.sites_per_block - 1)) == 0 &&
             e.sites_per_block * (nrhs / e.rpt) <= 256 && e.grid >= 0 && e.tchunk >= 1 &&
             g.L[3] % e.tchunk == 0 && tile_ok(g, e.tile_y, e.tile_z) &&
@@ -211,7 +211,7 @@ int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, cons
 int tune_hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, TuneEntry *best,
              hipStream_t st) {
     std::vector<TuneEntry> cand;
-    for (int rpt : {1, 2, 4}) {
+    for (int rpt : {1, 2, 3, 4}) {
         if (nrhs % rpt) continue;
         if (rpt > 1 && spinor_fmt(prec) == SpinorFmt::F64) continue;
         const int G = nrhs / rpt;
