@@ -281,7 +281,8 @@ def main():
     ap.add_argument("--prec", default="0,2,3", help="hop mode: precisions (0 FP64 .. 3 FP16)")
     ap.add_argument("--nrhs", default="1,12", help="hop mode: right-hand-side counts")
     ap.add_argument("--iters", type=int, default=20, help="hop mode: timed launches")
-    ap.add_argument("--tune", action="store_true", help="hop mode: autotune launch shapes")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune hop launch shapes on first use (solve: in the warmup)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -313,6 +314,8 @@ def main():
     lat = cola.Lattice(DIMS, KAPPA, bc, 0.0, cola.COLA_FLAG_TIMING)
     lat.set_gauge(U)
     assert lat.gauge_is_su3
+    if args.tune:
+        cola.cola_set_tuning(lat.h, 1)  # launch shapes measured on first use (warmup)
 
     def solve():
         return lat.cg(b, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP16_DEFECT, tol=TOL)
@@ -343,6 +346,8 @@ def main():
     if not args.no_fp64:
         lat64 = cola.Lattice(DIMS, KAPPA, bc, 0.0, cola.COLA_FLAG_TIMING)
         lat64.set_gauge(U)
+        if args.tune:
+            cola.cola_set_tuning(lat64.h, 1)
         b1 = b[:1].clone()
         lat64.cg(b1, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP64, tol=TOL)  # warm
         lat64.reset_stats()
@@ -376,7 +381,8 @@ def main():
         "config": {"workload": "wilson_eo_32x32x32x64_12rhs_fp16defect", "lattice": list(DIMS),
                    "kappa": KAPPA, "nrhs": 12, "sources": "point (12 spin-colour at origin)",
                    "solver": "lockstep 12-RHS CG, FP16 storage + FP64 defect correction",
-                   "tol": TOL, "parallelism": "none (1 GPU)"},
+                   "tol": TOL, "parallelism": "none (1 GPU)",
+                   "launch_shapes": "autotuned in warmup" if args.tune else "library defaults"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(), "hop_sources_sha256": hop_sources_sha256(),

@@ -86,6 +86,8 @@ int cola_create(cola_handle_t **hp, const int dims[4], double kappa, const doubl
     h->flags = flags;
     for (int mu = 0; mu < 4; ++mu) h->phase[mu] = {bc_phase[2 * mu], bc_phase[2 * mu + 1]};
     hipError_t e = hipGetDevice(&h->device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device);
     if (e == hipSuccess) e = hipMalloc(&h->partial, sizeof(double) * kMaxGrid * kMaxRhs);
     if (e == hipSuccess) e = hipMalloc(&h->counter, sizeof(unsigned) * 16);
     if (e == hipSuccess) e = hipMemset(h->counter, 0, sizeof(unsigned) * 16);
@@ -279,10 +281,10 @@ size_t cola_tune_dump(const cola_handle_t *h, char *buf, size_t len) {
         char e[256];
         snprintf(e, sizeof e,
                  "%s\"%s\": {\"rpt\": %d, \"sites_per_block\": %d, \"grid\": %d, "
-                 "\"tchunk\": %d, \"tile\": [%d, %d], \"ms\": %.6f}",
+                 "\"tchunk\": %d, \"tile\": [%d, %d], \"stage_links\": %d, \"ms\": %.6f}",
                  first ? "" : ", ", kv.first.c_str(), kv.second.rpt, kv.second.sites_per_block,
                  kv.second.grid, kv.second.tchunk, kv.second.tile_y, kv.second.tile_z,
-                 kv.second.ms);
+                 kv.second.stage, kv.second.ms);
         s += e;
         first = false;
     }

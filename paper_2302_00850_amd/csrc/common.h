@@ -88,7 +88,16 @@ struct HopArgs {
     // all x-rows of tile_y x tile_z (y, z) columns
     int tile_y, tile_z;
     FastDiv div_tcols, div_lt, div_lxh, div_ty, div_nty;
+    // the site's links staged in LDS by its first eight lanes (groups >= 8, one rhs per
+    // lane, sites_per_block <= 32, 12-real FP16 / FP32 links)
+    int stage_links;
+    // host only: when set, the launcher stores the kernel's resident blocks per CU here
+    // instead of launching
+    int *occupancy;
 };
+
+// Sites of one block when the hop stages each site's links in LDS.
+constexpr int kStageSites = 32;
 
 // Link chunk counts per format.
 constexpr int link_chunks(LinkFmt f) {

@@ -25,10 +25,11 @@ template <typename T>
 __device__ __forceinline__ cpx<T> scale(T s, cpx<T> a) {
     return {s * a.x, s * a.y};
 }
-// a * b
+// a * b, as explicit fused multiply-adds: the rounding does not depend on how the
+// compiler contracts the surrounding code (kernels that must agree bitwise share it)
 template <typename T>
 __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
-    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+    return {fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x)};
 }
 // acc + a * b
 template <typename T>
@@ -390,6 +391,23 @@ struct LinkT<LinkFmt::F16_12> {
     struct alignas(8) chunk { _Float16 a, b, c, d; };
 };
 
+// row 2 = conj(row 0 x row 1) of a 12-real link: with a = row 0, b = row 1 and
+// (k, k1, k2) cyclic, row2_k = conj(a_k1 b_k2 - a_k2 b_k1).  Written as explicit fused
+// multiply-adds, so every caller rounds the same way.
+template <typename T>
+__device__ __forceinline__ void rebuild_row2(cpx<T> u[3][3]) {
+    const cpx<T> *a = u[0], *b = u[1];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+        const T re = fma(a[k1].x, b[k2].x,
+                         fma(-a[k1].y, b[k2].y, fma(-a[k2].x, b[k1].x, a[k2].y * b[k1].y)));
+        const T im = fma(a[k1].x, b[k2].y,
+                         fma(a[k1].y, b[k2].x, fma(-a[k2].x, b[k1].y, -(a[k2].y * b[k1].x))));
+        u[2][k] = {re, -im};
+    }
+}
+
 // Load U_mu at checkerboard site i of parity p; row 2 rebuilt as conj(row0 x row1)
 // for the 12-real formats.
 // UNI: parity p is the same for every lane of the wavefront.
@@ -425,16 +443,7 @@ __device__ __forceinline__ void load_link(const void *gauge, int S, int p, int m
             u[(2 * k + 1) / 3][(2 * k + 1) % 3] = {(T)c.c, (T)c.d};
         }
     }
-    if constexpr (F != LinkFmt::F64_18) {
-        // row 2 = conj(row 0 x row 1)
-        const cpx<T> *a = u[0], *b = u[1];
-        const cpx<T> c0 = cmul(a[1], b[2]) - cmul(a[2], b[1]);
-        const cpx<T> c1 = cmul(a[2], b[0]) - cmul(a[0], b[2]);
-        const cpx<T> c2 = cmul(a[0], b[1]) - cmul(a[1], b[0]);
-        u[2][0] = {c0.x, -c0.y};
-        u[2][1] = {c1.x, -c1.y};
-        u[2][2] = {c2.x, -c2.y};
-    }
+    if constexpr (F != LinkFmt::F64_18) rebuild_row2(u);
 }
 
 // w = U h
@@ -625,6 +634,123 @@ __device__ __forceinline__ void mul_h2(const LinkH2 &L, const h2 h[3], cpx<float
         re = dot2(L.A[a][2], h[2], re);
         im = dot2(L.B[a][2], h[2], im);
         w[a] = {re, im};
+    }
+}
+
+// ------------------------------------------- links staged by the lanes of a site
+
+// In the multi-rhs hop the lanes of one site can split its eight links between them:
+// lane j < 8 loads and rebuilds link j (mu = j / 2, backward for odd j) once and leaves
+// it in LDS for all the site's lanes.  The direction is then a per-lane value, so these
+// helpers take it at run time without divergent branches.  A staged link is 18 words:
+// FP16 links as their dot2 operands (A then B, of U or U^H), FP32 links as the nine
+// complex entries of U.
+constexpr int kStageWords = 20;                  // per link (18 used, 16-byte multiple)
+constexpr int kStageSite = 8 * kStageWords + 4;  // per site (padding spreads LDS banks)
+
+// backward neighbour x - mu for a run-time mu: every candidate, then a select
+__device__ __forceinline__ uint32_t nb_bwd_rt(const Geom &g, uint32_t i, const int x[4], int mu) {
+    const uint32_t base = i - (uint32_t)(x[0] >> 1);
+    const int xb = x[0] == 0 ? g.L[0] - 1 : x[0] - 1;
+    const uint32_t n0 = base + (uint32_t)(xb >> 1);
+    const uint32_t n1 = x[1] == 0 ? i + (uint32_t)((g.L[1] - 1) * g.s1) : i - g.s1;
+    const uint32_t n2 = x[2] == 0 ? i + (uint32_t)((g.L[2] - 1) * g.s2) : i - g.s2;
+    const uint32_t n3 = x[3] == 0 ? i + (uint32_t)((g.L[3] - 1) * g.s3) : i - g.s3;
+    const uint32_t a = mu == 0 ? n0 : n1, b = mu == 2 ? n2 : n3;
+    return mu < 2 ? a : b;
+}
+
+// chunk k of U_mu at (p, i) for run-time p and mu: one descriptor over the whole packed
+// gauge field (below 2^31 bytes, checked on the host), per-lane byte offset
+template <LinkFmt F>
+__device__ __forceinline__ typename LinkT<F>::chunk load_chunk_rt(const void *gauge, int S, int p,
+                                                                  int mu, int k, uint32_t i) {
+    using CH = typename LinkT<F>::chunk;
+    constexpr int N = link_chunks(F);
+    const uint32_t bytes = 8u * (uint32_t)N * (uint32_t)S * (uint32_t)sizeof(CH);
+    const uint32_t off =
+        ((uint32_t)((p * 4 + mu) * N + k) * (uint32_t)S + i) * (uint32_t)sizeof(CH);
+    return bload<CH>(buf_u(gauge, bytes), off);
+}
+
+// Stage link (mu, back) of output site i (backward: U_mu at neighbour n, parity 1 - p).
+template <LinkFmt F>
+__device__ __forceinline__ void stage_link(const void *gauge, int S, int p, int mu, bool back,
+                                           uint32_t i, uint32_t n, uint32_t *dst) {
+    using CH = typename LinkT<F>::chunk;
+    static_assert(F == LinkFmt::F16_12 || F == LinkFmt::F32_12, "12-real links only");
+    const int pl = back ? 1 - p : p;
+    const uint32_t il = back ? n : i;
+    uint32_t w[kStageWords];
+    if constexpr (F == LinkFmt::F16_12) {
+        h2 u[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const CH c = load_chunk_rt<F>(gauge, S, pl, mu, k, il);
+            u[(2 * k) / 3][(2 * k) % 3] = h2{c.a, c.b};
+            u[(2 * k + 1) / 3][(2 * k + 1) % 3] = h2{c.c, c.d};
+        }
+        link_h2_row2(u);
+        LinkH2 Lf, Lb;
+        link_h2_prepare<false>(u, Lf);
+        link_h2_prepare<true>(u, Lb);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const h2 A = back ? Lb.A[a][b] : Lf.A[a][b];
+                const h2 B = back ? Lb.B[a][b] : Lf.B[a][b];
+                __builtin_memcpy(&w[3 * a + b], &A, 4);
+                __builtin_memcpy(&w[9 + 3 * a + b], &B, 4);
+            }
+    } else {
+        cpx<float> u[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const CH c = load_chunk_rt<F>(gauge, S, pl, mu, k, il);
+            u[(2 * k) / 3][(2 * k) % 3] = {c.a, c.b};
+            u[(2 * k + 1) / 3][(2 * k + 1) % 3] = {c.c, c.d};
+        }
+        rebuild_row2(u);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                __builtin_memcpy(&w[2 * (3 * a + b)], &u[a][b].x, 4);
+                __builtin_memcpy(&w[2 * (3 * a + b) + 1], &u[a][b].y, 4);
+            }
+    }
+    w[18] = w[19] = 0u;
+#pragma unroll
+    for (int k = 0; k < kStageWords; k += 4)
+        *(u32x4_t *)(dst + k) = u32x4_t{w[k], w[k + 1], w[k + 2], w[k + 3]};
+}
+
+// read back a staged link
+__device__ __forceinline__ void read_staged(const uint32_t *src, LinkH2 &L) {
+    uint32_t w[kStageWords];
+#pragma unroll
+    for (int k = 0; k < kStageWords; k += 4) {
+        const u32x4_t v = *(const u32x4_t *)(src + k);
+        w[k] = v.x, w[k + 1] = v.y, w[k + 2] = v.z, w[k + 3] = v.w;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        __builtin_memcpy(&L.A[k / 3][k % 3], &w[k], 4);
+        __builtin_memcpy(&L.B[k / 3][k % 3], &w[9 + k], 4);
+    }
+}
+__device__ __forceinline__ void read_staged(const uint32_t *src, cpx<float> u[3][3]) {
+    uint32_t w[kStageWords];
+#pragma unroll
+    for (int k = 0; k < kStageWords; k += 4) {
+        const u32x4_t v = *(const u32x4_t *)(src + k);
+        w[k] = v.x, w[k + 1] = v.y, w[k + 2] = v.z, w[k + 3] = v.w;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        __builtin_memcpy(&u[k / 3][k % 3].x, &w[2 * k], 4);
+        __builtin_memcpy(&u[k / 3][k % 3].y, &w[2 * k + 1], 4);
     }
 }
 

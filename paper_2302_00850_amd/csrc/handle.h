@@ -16,15 +16,17 @@ namespace cola {
 
 constexpr int kMaxRhs = 16;
 constexpr int kMaxGrid = 65536;
-constexpr int kReduceGrid = 2048;  // blocks of a launch that reduces
+constexpr int kReduceGrid = 2048;  // most blocks of a launch that reduces
 
 struct TuneEntry {
     int rpt = 1;
     int sites_per_block = 64;
-    int grid = 0;    // 0: one block per sites_per_block site columns
+    int grid = 0;    // 0: one block per sites_per_block site columns; -1: the blocks
+                     // resident at once (grid-stride loop, no tail of late blocks)
     int tchunk = 1;  // timeslices walked by one lane
     int tile_y = 0;  // spatial tile (all x-rows x tile_y x tile_z); 0 = lexicographic
     int tile_z = 0;
+    int stage = 0;   // links staged in LDS by the lanes of a site (see stage_ok)
     double ms = 0;
 };
 
@@ -42,6 +44,8 @@ struct cola_handle {
     cola::Cplx64 phase[4];
     unsigned flags = 0;
     int device = 0;
+    int num_cu = 0;  // compute units of the device
+    std::map<std::string, int> occupancy;  // resident blocks per CU by launch variant
 
     // packed gauge fields by cola::LinkFmt
     void *gauge[4] = {nullptr, nullptr, nullptr, nullptr};

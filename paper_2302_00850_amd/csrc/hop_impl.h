@@ -30,11 +30,12 @@ namespace cola {
 // lane's RPT right-hand sides at checkerboard site i (coordinates x).  A template, so
 // the eight directions are unrolled by construction and every spin-projection branch
 // resolves at compile time.
-template <int MU, int DIR, SpinorFmt SF, LinkFmt LF, int RPT, bool RPH>
+template <int MU, int DIR, SpinorFmt SF, LinkFmt LF, int RPT, bool RPH, bool SHL>
 __device__ __forceinline__ void hop_dir(const HopArgs &a, const SpinorBlock<SF, true> &in, int p,
                                         uint32_t i, const int x[4], uint32_t j,
                                         typename SpinorT<SF>::real sg_f,
-                                        cpx<typename SpinorT<SF>::real> acc[RPT][12]) {
+                                        cpx<typename SpinorT<SF>::real> acc[RPT][12],
+                                        const uint32_t *staged) {
     using T = typename SpinorT<SF>::real;
     using C = cpx<T>;
     const Geom &g = a.g;
@@ -59,7 +60,10 @@ __device__ __forceinline__ void hop_dir(const HopArgs &a, const SpinorBlock<SF, 
         // prepared once for the lane's RPT right-hand sides, which are adjacent in
         // memory: one wide load per component.
         LinkH2 L;
-        load_link_h2<dir == 1>(a.gauge, g.S, dir == 0 ? p : 1 - p, mu, dir == 0 ? i : n, L);
+        if constexpr (SHL)
+            read_staged(staged + (2 * MU + DIR) * kStageWords, L);
+        else
+            load_link_h2<dir == 1>(a.gauge, g.S, dir == 0 ? p : 1 - p, mu, dir == 0 ? i : n, L);
         h2 s[RPT][12];
         float scl[RPT];
         in.template load_raw_h2_group<RPT>(n, j * RPT, s, scl);
@@ -78,7 +82,10 @@ __device__ __forceinline__ void hop_dir(const HopArgs &a, const SpinorBlock<SF, 
         }
     } else {
         C u[3][3];
-        load_link<LF, T>(a.gauge, g.S, dir == 0 ? p : 1 - p, mu, dir == 0 ? i : n, u);
+        if constexpr (SHL && LF == LinkFmt::F32_12)
+            read_staged(staged + (2 * MU + DIR) * kStageWords, u);
+        else
+            load_link<LF, T>(a.gauge, g.S, dir == 0 ? p : 1 - p, mu, dir == 0 ? i : n, u);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             C s[12], h[6], w[6];
@@ -108,11 +115,13 @@ __device__ __forceinline__ void hop_dir(const HopArgs &a, const SpinorBlock<SF, 
         for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(acc[r][c].x), "+v"(acc[r][c].y));
 }
 
-template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, int EPI, bool RPH>
+template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, int EPI, bool RPH, bool SHL>
 __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     using T = typename SpinorT<SF>::real;
     using C = cpx<T>;
     extern __shared__ double red[];
+    // SHL: the site's eight links staged in LDS by its first eight lanes
+    __shared__ __attribute__((aligned(16))) uint32_t stage[SHL ? kStageSites * kStageSite : 4];
     const Geom &g = a.g;
     const int p = a.parity;
     const SpinorBlock<SF, true> in(a.in, g.S, a.nrhs);
@@ -127,9 +136,13 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t ncol = (uint32_t)g.s3;  // checkerboard sites of one timeslice
     // Lane w owns rhs group j of spatial column c in time chunk k and walks the chunk's
-    // timeslices: the spinors its t-neighbours need were fetched one step earlier.
-    for (uint32_t w = lb * blockDim.x + threadIdx.x; w < a.total; w += stride)
+    // timeslices: the spinors its t-neighbours need were fetched one step earlier.  The
+    // trip count is the same for every lane of a block (lanes past the end idle), so the
+    // staging barriers are reached by all.
+    for (uint32_t base = lb * blockDim.x; base < a.total; base += stride)
     for (int tt = 0; tt < a.tchunk; ++tt) {
+        const uint32_t w = base + threadIdx.x;
+        const bool valid = w < a.total;
         const uint32_t q = fdiv(w, a.div_groups);
         const uint32_t j = w - q * (uint32_t)a.groups;
         uint32_t i;
@@ -153,20 +166,35 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
         }
         int x[4];
         site_coords(g, i, p, x);
+        const uint32_t *staged = nullptr;
+        if constexpr (SHL) {
+            // block = sites_per_block sites x groups lanes (groups >= 8), whole sites
+            const uint32_t slot = threadIdx.x / (uint32_t)a.groups;
+            uint32_t *mine = stage + slot * kStageSite;
+            __syncthreads();  // the previous site's links are no longer read
+            if (valid && j < 8) {
+                const int mu = (int)(j >> 1);
+                const uint32_t n = nb_bwd_rt(g, i, x, mu);
+                stage_link<LF>(a.gauge, g.S, p, mu, (j & 1) != 0, i, n, mine + j * kStageWords);
+            }
+            __syncthreads();
+            staged = mine;
+        }
+        if (!valid) continue;
         C acc[RPT][12];
 #pragma unroll
         for (int r = 0; r < RPT; ++r)
 #pragma unroll
             for (int c = 0; c < 12; ++c) acc[r][c] = {(T)0, (T)0};
 
-        hop_dir<0, 0, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
-        hop_dir<0, 1, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
-        hop_dir<1, 0, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
-        hop_dir<1, 1, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
-        hop_dir<2, 0, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
-        hop_dir<2, 1, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
-        hop_dir<3, 0, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
-        hop_dir<3, 1, SF, LF, RPT, RPH>(a, in, p, i, x, j, sg_f, acc);
+        hop_dir<0, 0, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
+        hop_dir<0, 1, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
+        hop_dir<1, 0, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
+        hop_dir<1, 1, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
+        hop_dir<2, 0, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
+        hop_dir<2, 1, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
+        hop_dir<3, 0, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
+        hop_dir<3, 1, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
 
         const T ca = (T)a.a;
 #pragma unroll
@@ -219,22 +247,27 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     }
 }
 
-template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, int EPI, bool RPH>
+template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, int EPI, bool RPH, bool SHL>
 hipError_t hop_launch_t(const HopArgs &a, int grid, int block, hipStream_t st) {
     const size_t shm = a.want_norm ? (size_t)a.sites_per_block * a.nrhs * sizeof(double) : 0;
-    hipLaunchKernelGGL((hop_kernel<SF, LF, CR, RPT, EPI, RPH>), dim3(grid), dim3(block), shm, st,
-                       a);
+    if (a.occupancy)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            a.occupancy, hop_kernel<SF, LF, CR, RPT, EPI, RPH, SHL>, block, shm);
+    hipLaunchKernelGGL((hop_kernel<SF, LF, CR, RPT, EPI, RPH, SHL>), dim3(grid), dim3(block), shm,
+                       st, a);
     return hipGetLastError();
 }
 
-template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, bool RPH>
+template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, bool RPH, bool SHL = false>
 hipError_t hop_launch_epi(const HopArgs &a, int grid, int block, hipStream_t st) {
     switch (a.epi) {
-        case EPI_NONE: return hop_launch_t<SF, LF, CR, RPT, EPI_NONE, RPH>(a, grid, block, st);
-        case EPI_XPAY: return hop_launch_t<SF, LF, CR, RPT, EPI_XPAY, RPH>(a, grid, block, st);
-        case EPI_CLOV: return hop_launch_t<SF, LF, CR, RPT, EPI_CLOV, RPH>(a, grid, block, st);
-        case EPI_CLOV_XPAY: return hop_launch_t<SF, LF, CR, RPT, EPI_CLOV_XPAY, RPH>(a, grid, block, st);
-        case EPI_XPAY_CLOV: return hop_launch_t<SF, LF, CR, RPT, EPI_XPAY_CLOV, RPH>(a, grid, block, st);
+        case EPI_NONE: return hop_launch_t<SF, LF, CR, RPT, EPI_NONE, RPH, SHL>(a, grid, block, st);
+        case EPI_XPAY: return hop_launch_t<SF, LF, CR, RPT, EPI_XPAY, RPH, SHL>(a, grid, block, st);
+        case EPI_CLOV: return hop_launch_t<SF, LF, CR, RPT, EPI_CLOV, RPH, SHL>(a, grid, block, st);
+        case EPI_CLOV_XPAY:
+            return hop_launch_t<SF, LF, CR, RPT, EPI_CLOV_XPAY, RPH, SHL>(a, grid, block, st);
+        case EPI_XPAY_CLOV:
+            return hop_launch_t<SF, LF, CR, RPT, EPI_XPAY_CLOV, RPH, SHL>(a, grid, block, st);
     }
     return hipErrorInvalidValue;
 }
@@ -245,6 +278,15 @@ hipError_t hop_launch_fmt(const HopArgs &a, int rpt, int grid, int block, hipStr
     for (int mu = 0; mu < 4; ++mu) real_phase &= a.phase[mu].y == 0.0;
     // several rhs per lane only where the accumulators fit (FP64 keeps one)
     constexpr bool multi = SF != SpinorFmt::F64;
+    // links staged in LDS by the site's lanes: 12-real FP16 / FP32 links, one rhs per lane
+    constexpr bool stageable = LF == LinkFmt::F16_12 || LF == LinkFmt::F32_12;
+    if constexpr (stageable) {
+        if (a.stage_links && rpt == 1) {
+            if (real_phase) return hop_launch_epi<SF, LF, CR, 1, true, true>(a, grid, block, st);
+            return hop_launch_epi<SF, LF, CR, 1, false, true>(a, grid, block, st);
+        }
+    }
+    if (a.stage_links) return hipErrorInvalidValue;
     if (real_phase) {
         if (rpt == 1) return hop_launch_epi<SF, LF, CR, 1, true>(a, grid, block, st);
         if constexpr (multi) {

@@ -118,7 +118,7 @@ void shape_for(const TuneEntry &t, int Vh, int nrhs, int *groups, int *T, int *g
     *block = *T * *groups;
     const long cols = Vh / t.tchunk;
     long g = (cols + *T - 1) / *T;
-    if (t.grid > 0 && t.grid < g) g = t.grid;
+    if (t.grid > 0 && t.grid < g) g = t.grid;  // t.grid < 0: resident cap applied later
     if (g > kMaxGrid) g = kMaxGrid;
     *grid = (int)std::max(1L, g);
 }
@@ -139,7 +139,16 @@ bool tile_ok(const Geom &g, int ty, int tz) {
     return ty > 0 && tz > 0 && g.L[1] % ty == 0 && g.L[2] % tz == 0;
 }
 
-TuneEntry default_entry(const Geom &g, int nrhs) {
+// Link staging needs eight lanes per site (one rhs each), whole sites of at most
+// kStageSites per block, a 12-real FP16 or FP32 field and a packed field addressable
+// with 32-bit byte offsets.
+bool stage_ok(const Geom &g, int prec, int nrhs, const TuneEntry &t) {
+    if (prec != COLA_FP16 && prec != COLA_FP32) return false;
+    const double bytes = 8.0 * 3 * g.S * (prec == COLA_FP16 ? 8 : 16);
+    return t.rpt == 1 && nrhs >= 8 && t.sites_per_block <= kStageSites && bytes < 2147483648.0;
+}
+
+TuneEntry default_entry(const Geom &g, int prec, int nrhs) {
     TuneEntry t;
     t.rpt = 1;
     const int G = nrhs;
@@ -148,18 +157,34 @@ TuneEntry default_entry(const Geom &g, int nrhs) {
     t.sites_per_block = T;
     t.grid = 0;
     t.tchunk = default_tchunk(g, G);
+    // Spatial tiles for the multi-rhs FP16 / FP32 hops, where they measured fastest on a
+    // 32^3 x 64 lattice (16x8 (y, z) columns walked through t).  Lattices the tile does
+    // not divide, and single-rhs hops, keep the time-chunk order.
+    int ty = 0, tz = 0;
+    if (nrhs >= 4 && (prec == COLA_FP16 || prec == COLA_FP32)) ty = 16, tz = 8;
+    if (ty > 0 && tile_ok(g, ty, tz)) {
+        t.tile_y = ty;
+        t.tile_z = tz;
+        t.tchunk = 1;
+    }
+    t.stage = stage_ok(g, prec, nrhs, t) ? 1 : 0;
     // Measurement knob: COLA_HOP_SHAPE="rpt,sites_per_block,grid,tchunk" pins the
     // untuned launch shape (ignored unless every field is valid for this launch).
     if (const char *env = getenv("COLA_HOP_SHAPE")) {
         TuneEntry e;
-        const int n = sscanf(env, "%d,%d,%d,%d,%d,%d", &e.rpt, &e.sites_per_block, &e.grid,
-                             &e.tchunk, &e.tile_y, &e.tile_z);
-        if ((n == 4 || n == 6) && (e.rpt >= 1 && e.rpt <= 4) && nrhs % e.rpt == 0 &&
+        e.stage = -1;
+        const int n = sscanf(env, "%d,%d,%d,%d,%d,%d,%d", &e.rpt, &e.sites_per_block, &e.grid,
+                             &e.tchunk, &e.tile_y, &e.tile_z, &e.stage);
+        if ((n == 4 || n == 6 || n == 7) && (e.rpt >= 1 && e.rpt <= 4) && nrhs % e.rpt == 0 &&
             e.sites_per_block >= 1 && (e.sites_per_block & (e.sites_per_block - 1)) == 0 &&
-            e.sites_per_block * (nrhs / e.rpt) <= 256 && e.grid >= 0 && e.tchunk >= 1 &&
+            e.sites_per_block * (nrhs / e.rpt) <= 256 && e.grid >= -1 && e.tchunk >= 1 &&
             g.L[3] % e.tchunk == 0 && tile_ok(g, e.tile_y, e.tile_z) &&
-            (e.tile_y == 0 || e.tchunk == 1))
+            (e.tile_y == 0 || e.tchunk == 1)) {
+            // staging as asked where possible, else the default rule
+            const bool ok = stage_ok(g, prec, nrhs, e);
+            e.stage = e.stage < 0 ? (ok ? 1 : 0) : (e.stage && ok ? 1 : 0);
             t = e;
+        }
     }
     return t;
 }
@@ -174,8 +199,6 @@ int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, cons
     a.nrhs = nrhs;
     int groups, T, grid, block;
     shape_for(te, h->g.Vh, nrhs, &groups, &T, &grid, &block);
-    // launches that reduce keep the partial-sum array short (grid-stride instead)
-    if (c.norm_result && grid > kReduceGrid) grid = kReduceGrid;
     a.groups = groups;
     a.div_groups = make_fastdiv((uint32_t)groups);
     a.epi = c.epi;
@@ -196,6 +219,7 @@ int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, cons
     a.div_ncol = make_fastdiv((uint32_t)h->g.s3);
     a.tile_y = te.tile_y;
     a.tile_z = te.tile_z;
+    a.stage_links = te.stage;
     if (te.tile_y > 0) {
         const Geom &g = h->g;
         a.div_tcols = make_fastdiv((uint32_t)(g.Lxh * te.tile_y * te.tile_z));
@@ -203,6 +227,30 @@ int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, cons
         a.div_lxh = make_fastdiv((uint32_t)g.Lxh);
         a.div_ty = make_fastdiv((uint32_t)te.tile_y);
         a.div_nty = make_fastdiv((uint32_t)(g.L[1] / te.tile_y));
+    }
+    // Launches that reduce keep the partial-sum array short, and explicit resident
+    // grids (te.grid < 0) ask for it: then the grid is the number of blocks the device
+    // holds at once (a grid-stride loop), so no block starts after others have done
+    // all their passes.
+    if (te.grid < 0 || (c.norm_result && grid > kReduceGrid)) {
+        char key[96];
+        bool rph = true;
+        for (int mu = 0; mu < 4; ++mu) rph &= h->phase[mu].y == 0.0;
+        snprintf(key, sizeof key, "%d:%d:%d:%d:%d:%d:%d:%d", prec, te.rpt, c.epi, a.want_norm,
+                 te.stage, block, nrhs, (int)rph);
+        auto it = h->occupancy.find(key);
+        int occ = 0;
+        if (it != h->occupancy.end()) {
+            occ = it->second;
+        } else {
+            a.occupancy = &occ;
+            COLA_HIP(h, launch_hop(a, link_fmt(prec), te.rpt, grid, block, st));
+            a.occupancy = nullptr;
+            h->occupancy[key] = occ;
+        }
+        long cap = (long)std::max(1, occ) * std::max(1, h->num_cu);
+        if (c.norm_result) cap = std::min<long>(cap, kReduceGrid);
+        if (grid > cap) grid = (int)cap;
     }
     COLA_HIP(h, launch_hop(a, link_fmt(prec), te.rpt, grid, block, st));
     return COLA_OK;
@@ -215,11 +263,15 @@ int tune_hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, TuneEntry *
         if (nrhs % rpt) continue;
         if (rpt > 1 && spinor_fmt(prec) == SpinorFmt::F64) continue;
         const int G = nrhs / rpt;
+        // blocks of whole wavefronts when some block size allows it
+        bool whole = false;
+        for (int T : {4, 8, 16, 32, 64, 128, 256}) whole |= T * G <= 256 && (T * G) % 64 == 0;
         for (int T : {4, 8, 16, 32, 64, 128, 256}) {
             if (T * G > 256 || T * G < 64) continue;
+            if (whole && (T * G) % 64 != 0) continue;
             for (int tc : {1, 2, 4, 8, 16}) {
                 if (h->g.L[3] % tc) continue;
-                for (int grid : {0, 2048}) {
+                for (int grid : {0, -1}) {
                     TuneEntry t;
                     t.rpt = rpt;
                     t.sites_per_block = T;
@@ -239,6 +291,14 @@ int tune_hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, TuneEntry *
                 cand.push_back(t);
             }
         }
+    }
+    // each shape also with the site's links staged in LDS, where that applies
+    const size_t n0 = cand.size();
+    for (size_t k = 0; k < n0; ++k) {
+        if (!stage_ok(h->g, prec, nrhs, cand[k])) continue;
+        TuneEntry t = cand[k];
+        t.stage = 1;
+        cand.push_back(t);
     }
     hipEvent_t e0, e1;
     COLA_HIP(h, hipEventCreate(&e0));
@@ -308,7 +368,7 @@ int hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, hipStream_t st) 
         COLA_TRY(tune_hop(h, c, prec, nrhs, &te, st));
         h->tune[key] = te;
     } else {
-        te = default_entry(h->g, nrhs);
+        te = default_entry(h->g, prec, nrhs);
     }
     const bool timed = (h->flags & COLA_FLAG_TIMING) != 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;

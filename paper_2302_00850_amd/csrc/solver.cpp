@@ -263,8 +263,9 @@ int solve_reliable(const Ctx &c, int sloppy_prec, const cola_cg_params_t &p, voi
 
 // ---------------------------------------------------------------- defect correction
 
-int inner_cg(const Ctx &c, int prec, void *x, void *r, void *pv, void *ap, double inner_tol2,
-             int max_it, std::vector<int> act, int check, int *iters, int *status) {
+int inner_cg(const Ctx &c, int prec, void *x, void *r, void *pv, void *ap,
+             const std::vector<double> &inner_tol2, int max_it, std::vector<int> act, int check,
+             int *iters, int *status) {
     cola_handle_t *h = c.h;
     const BlasShape sh = c.shape();
     const SpinorFmt fp = spinor_fmt(prec);
@@ -286,7 +287,7 @@ int inner_cg(const Ctx &c, int prec, void *x, void *r, void *pv, void *ap, doubl
             }
             bool any = false;
             for (int q = 0; q < c.R; ++q) {
-                if (act[q] && rho[q] <= inner_tol2) act[q] = 0;
+                if (act[q] && rho[q] <= inner_tol2[q]) act[q] = 0;
                 any |= act[q] != 0;
             }
             if (!any) break;
@@ -389,8 +390,9 @@ int upload_mat(const Ctx &c, const std::vector<cd> &Z, double *dev, double *host
 //   Q = A P; alpha = (P^H Q)^-1 (R^H R); E += P alpha; R -= Q alpha;
 //   beta = (R^H R)_old^-1 (R^H R)_new; P = R + P beta.
 // Stops when every active column's |R_q|^2 <= inner_tol2 (the columns start at 1).
-int inner_block_cg(const Ctx &c, int prec, void *x32, void *r32, double inner_tol2, int max_it,
-                   std::vector<int> act, int *iters, int *status) {
+int inner_block_cg(const Ctx &c, int prec, void *x32, void *r32,
+                   const std::vector<double> &inner_tol2, int max_it, std::vector<int> act,
+                   int *iters, int *status) {
     cola_handle_t *h = c.h;
     const int n = c.R;
     const SpinorFmt fp = spinor_fmt(prec);
@@ -429,7 +431,7 @@ int inner_block_cg(const Ctx &c, int prec, void *x32, void *r32, double inner_to
         for (int q = 0; q < n; ++q) {
             const double d = rho_new[(size_t)q * n + q].real();
             bad |= !std::isfinite(d);
-            any |= act[q] && d > inner_tol2;
+            any |= act[q] && d > inner_tol2[q];
         }
         if (bad) {
             *status = COLA_BREAKDOWN;
@@ -480,6 +482,12 @@ int solve_defect(const Ctx &c, int inner_prec, const cola_cg_params_t &p, void *
             o->status = COLA_NOT_CONVERGED;
             return COLA_OK;
         }
+        // Inner target per column (relative to |R|): the scheme's reduction, relaxed to
+        // ten times below what the column still needs so the last cycle does not solve
+        // far past the tolerance.
+        std::vector<double> itol2(c.R, itol * itol);
+        for (int q = 0; q < c.R; ++q)
+            if (act[q] && tr[q] > 0) itol2[q] = std::max(itol * itol, 1e-2 * thr[q] / tr[q]);
         if (o->outer > 0 && worst > 0.5) {
             if (++slow >= 3 && prec == COLA_FP16) {
                 prec = COLA_FP32;
@@ -503,11 +511,11 @@ int solve_defect(const Ctx &c, int inner_prec, const cola_cg_params_t &p, void *
         if (!c.full) COLA_TRY(zero_pi2(c));
         int its = 0, st = COLA_OK;
         if (p.block)
-            COLA_TRY(inner_block_cg(c, prec, x32, r32, itol * itol, p.max_iter - o->iterations,
-                                    act, &its, &st));
+            COLA_TRY(inner_block_cg(c, prec, x32, r32, itol2, p.max_iter - o->iterations, act,
+                                    &its, &st));
         else
-            COLA_TRY(inner_cg(c, prec, x32, r32, pv, ap, itol * itol, p.max_iter - o->iterations,
-                              act, check, &its, &st));
+            COLA_TRY(inner_cg(c, prec, x32, r32, pv, ap, itol2, p.max_iter - o->iterations, act,
+                              check, &its, &st));
         o->iterations += its;
         ++o->outer;
         if (st != COLA_OK) {

@@ -177,7 +177,7 @@ def test_dslash_argument_errors(fields):
 
 
 SHAPES = ["1,16,0,2", "1,16,0,5", "1,64,0,10", "1,16,0,1,2,2", "1,8,0,1,4,2", "1,32,3,1,4,4",
-          "2,16,0,2", "4,8,0,1,2,4"]
+          "2,16,0,2", "4,8,0,1,2,4", "1,16,-1,2", "3,16,0,1,2,2"]
 
 
 @pytest.mark.parametrize("prec", [0, 2, 3])
@@ -207,6 +207,37 @@ def test_hop_identical_across_launch_shapes(fields, prec, monkeypatch):
     out2 = lat.empty_packed(prec, nrhs, 0)
     lat.dslash(out2, a, cola.COLA_OP_SCHUR, 0, prec, nrhs)
     assert torch.equal(out, out2)
+
+
+STAGED = ["1,16,0,1,0,0,1", "1,16,0,1,2,2,1", "1,8,7,1,0,0,1", "1,16,3,2,0,0,1",
+          "1,16,0,5,0,0,1", "1,32,0,1,2,4,1", "1,16,-1,1,2,2,1"]
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+@pytest.mark.parametrize("op", ["hop", "schur"])
+def test_staged_links_identical(fields, prec, op, monkeypatch):
+    """With 12 rhs the lanes of a site can stage its links in LDS; the result is bitwise
+    the one of per-lane link loads, for several block sizes, grid-stride loops with a
+    ragged last pass, time chunks and tiles (and with the fused norm of the Schur op)."""
+    U, psi = fields
+    nrhs = 12
+    lat = _lat(U, GENERIC)
+    code = cola.COLA_OP_HOP if op == "hop" else cola.COLA_OP_SCHUR
+    pin = lat.pack(_cuda(psi), prec, 1 if op == "hop" else 0)
+    monkeypatch.setenv("COLA_HOP_SHAPE", "1,16,0,1,0,0,0")
+    ref = lat.empty_packed(prec, nrhs, 0)
+    lat.dslash(ref, pin, code, 0, prec, nrhs)
+    for shape in STAGED:
+        monkeypatch.setenv("COLA_HOP_SHAPE", shape)
+        out = lat.empty_packed(prec, nrhs, 0)
+        lat.dslash(out, pin, code, 0, prec, nrhs)
+        assert torch.equal(out, ref), shape
+    # and it is the oracle's hop
+    if op == "hop":
+        got = lat.unpack(ref, prec, nrhs, 0).cpu().numpy()
+        src = np.where(~_even(DIMS), lat.unpack(pin, prec, nrhs, 1).cpu().numpy(), 0)
+        want = np.where(_even(DIMS), oracle.hop(U, src, GENERIC), 0)
+        assert rel(np.where(_even(DIMS), got, 0), want) <= TOL[prec]
 
 
 def test_hop_deterministic_and_timing_stats(fields):
