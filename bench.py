@@ -282,7 +282,7 @@ def main():
     ap.add_argument("--nrhs", default="1,12", help="hop mode: right-hand-side counts")
     ap.add_argument("--iters", type=int, default=20, help="hop mode: timed launches")
     ap.add_argument("--tune", action="store_true",
-                    help="autotune hop launch shapes on first use (solve: in the warmup)")
+                    help="autotune hop launch shapes on first use (solve mode: in the warmup)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -314,7 +314,8 @@ def main():
     lat = cola.Lattice(DIMS, KAPPA, bc, 0.0, cola.COLA_FLAG_TIMING)
     lat.set_gauge(U)
     assert lat.gauge_is_su3
-    if args.tune:
+    tune = args.tune and args.warmup > 0  # tuning stays out of the timed steps
+    if tune:
         cola.cola_set_tuning(lat.h, 1)  # launch shapes measured on first use (warmup)
 
     def solve():
@@ -346,7 +347,7 @@ def main():
     if not args.no_fp64:
         lat64 = cola.Lattice(DIMS, KAPPA, bc, 0.0, cola.COLA_FLAG_TIMING)
         lat64.set_gauge(U)
-        if args.tune:
+        if tune:
             cola.cola_set_tuning(lat64.h, 1)
         b1 = b[:1].clone()
         lat64.cg(b1, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP64, tol=TOL)  # warm
@@ -382,7 +383,7 @@ def main():
                    "kappa": KAPPA, "nrhs": 12, "sources": "point (12 spin-colour at origin)",
                    "solver": "lockstep 12-RHS CG, FP16 storage + FP64 defect correction",
                    "tol": TOL, "parallelism": "none (1 GPU)",
-                   "launch_shapes": "autotuned in warmup" if args.tune else "library defaults"},
+                   "launch_shapes": "autotuned in warmup" if tune else "library defaults"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(), "hop_sources_sha256": hop_sources_sha256(),

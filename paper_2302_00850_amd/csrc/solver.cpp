@@ -263,13 +263,14 @@ int solve_reliable(const Ctx &c, int sloppy_prec, const cola_cg_params_t &p, voi
 
 // ---------------------------------------------------------------- defect correction
 
-int inner_cg(const Ctx &c, int prec, void *x, void *r, void *pv, void *ap,
+// CG iterations on the normal system in precision prec (p, Ap in that storage; x and r
+// in storage fx, FP32 arithmetic throughout).
+int inner_cg(const Ctx &c, int prec, SpinorFmt fx, void *x, void *r, void *pv, void *ap,
              const std::vector<double> &inner_tol2, int max_it, std::vector<int> act, int check,
              int *iters, int *status) {
     cola_handle_t *h = c.h;
     const BlasShape sh = c.shape();
     const SpinorFmt fp = spinor_fmt(prec);
-    const SpinorFmt fx = SpinorFmt::F32;
     const Reduce red_new = reduce_into(h, RHO_NEW);
     COLA_TRY(write_active(c, act));
     std::vector<double> rho(c.R);
@@ -503,19 +504,28 @@ int solve_defect(const Ctx &c, int inner_prec, const cola_cg_params_t &p, void *
         COLA_TRY(vec(c, "dp", fp, &pv));
         COLA_TRY(vec(c, "dap", fp, &ap));
         const Reduce red_rho = reduce_into(h, RHO);
-        // r32 = R / |R|, rho = |r32|^2 ; p = r32 ; x32 = 0
-        COLA_HIP(h, launch_convert(sh, SpinorFmt::F32, SpinorFmt::F64, r32, r64, c.slot(SCALE), 1,
-                                   &red_rho, c.st));
-        COLA_HIP(h, launch_convert(sh, fp, SpinorFmt::F32, pv, r32, nullptr, 0, nullptr, c.st));
-        COLA_HIP(h, hipMemsetAsync(x32, 0, c.bytes(SpinorFmt::F32), c.st));
+        // Inner vectors: r = R / |R| (rho = |r|^2), p = r, x = 0.  Block CG keeps x and r in
+        // FP32; the lockstep solver stores them like p, in the inner precision (FP16 rounds
+        // them to about 5e-4 per update, far below the inner solve's 1e-2 reduction, and
+        // saves a third of the bytes of the update kernels).
+        const SpinorFmt fxr = p.block ? SpinorFmt::F32 : fp;
+        void *xs = x32, *rs = r32;
+        if (fxr != SpinorFmt::F32) {
+            COLA_TRY(vec(c, "dx", fxr, &xs));
+            COLA_TRY(vec(c, "dr", fxr, &rs));
+        }
+        COLA_HIP(h, launch_convert(sh, fxr, SpinorFmt::F64, rs, r64, c.slot(SCALE), 1, &red_rho,
+                                   c.st));
+        COLA_HIP(h, launch_convert(sh, fp, fxr, pv, rs, nullptr, 0, nullptr, c.st));
+        COLA_HIP(h, hipMemsetAsync(xs, 0, c.bytes(fxr), c.st));
         if (!c.full) COLA_TRY(zero_pi2(c));
         int its = 0, st = COLA_OK;
         if (p.block)
             COLA_TRY(inner_block_cg(c, prec, x32, r32, itol2, p.max_iter - o->iterations, act,
                                     &its, &st));
         else
-            COLA_TRY(inner_cg(c, prec, x32, r32, pv, ap, itol2, p.max_iter - o->iterations, act,
-                              check, &its, &st));
+            COLA_TRY(inner_cg(c, prec, fxr, xs, rs, pv, ap, itol2, p.max_iter - o->iterations,
+                              act, check, &its, &st));
         o->iterations += its;
         ++o->outer;
         if (st != COLA_OK) {
@@ -523,7 +533,7 @@ int solve_defect(const Ctx &c, int inner_prec, const cola_cg_params_t &p, void *
             return COLA_OK;
         }
         // X += |R| E
-        COLA_HIP(h, launch_accum(sh, SpinorFmt::F32, x64, x32, c.slot(SCALE), 0, c.st));
+        COLA_HIP(h, launch_accum(sh, fxr, x64, xs, c.slot(SCALE), 0, c.st));
     }
 }
 
