@@ -88,9 +88,9 @@ int cola_create(cola_handle_t **hp, const int dims[4], double kappa, const doubl
     hipError_t e = hipGetDevice(&h->device);
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device);
-    if (e == hipSuccess) e = hipMalloc(&h->partial, sizeof(double) * kMaxGrid * kMaxRhs);
-    if (e == hipSuccess) e = hipMalloc(&h->counter, sizeof(unsigned) * 16);
-    if (e == hipSuccess) e = hipMemset(h->counter, 0, sizeof(unsigned) * 16);
+    if (e == hipSuccess) e = hipMalloc(&h->partial, sizeof(double) * kRedPartialDoubles);
+    if (e == hipSuccess) e = hipMalloc(&h->counter, sizeof(unsigned) * kRedCounters);
+    if (e == hipSuccess) e = hipMemset(h->counter, 0, sizeof(unsigned) * kRedCounters);
     if (e == hipSuccess) e = hipMalloc(&h->scal, sizeof(double) * kScalSlots * kMaxRhs);
     if (e == hipSuccess) e = hipMemset(h->scal, 0, sizeof(double) * kScalSlots * kMaxRhs);
     if (e == hipSuccess) e = hipMalloc(&h->active, sizeof(int) * kMaxRhs);

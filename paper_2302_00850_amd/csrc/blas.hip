@@ -246,6 +246,41 @@ struct CloverFn {
 
 }  // namespace
 
+namespace {
+
+// result[q] = sum over b < nblocks of partial[b][q], in a fixed order: one block per
+// column, thread t adds blocks t, t + 256, ... and an LDS tree adds the threads.
+__global__ void __launch_bounds__(256) reduce_partials_kernel(const double *partial,
+                                                              int nblocks, int width,
+                                                              double *result) {
+    __shared__ double red[256];
+    const int q = blockIdx.x;
+    const int t = threadIdx.x;
+    double a0 = 0.0, a1 = 0.0;
+    int b = t;
+    for (; b + 256 < nblocks; b += 512) {
+        a0 += partial[(size_t)b * width + q];
+        a1 += partial[(size_t)(b + 256) * width + q];
+    }
+    for (; b < nblocks; b += 256) a0 += partial[(size_t)b * width + q];
+    red[t] = a0 + a1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) result[q] = red[0];
+}
+
+}  // namespace
+
+hipError_t launch_reduce_partials(const double *partial, int nblocks, int width, double *result,
+                                  hipStream_t st) {
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(width), dim3(256), 0, st, partial, nblocks,
+                       width, result);
+    return hipGetLastError();
+}
+
 BlasShape blas_shape(const Geom &g, int nrhs, int nblk) {
     BlasShape b;
     b.S = g.S;

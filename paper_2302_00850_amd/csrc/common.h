@@ -96,6 +96,18 @@ struct HopArgs {
     int *occupancy;
 };
 
+// Deterministic reductions: per-block partials are summed per group of kRedGroup blocks
+// by the group's last block, then the group sums by the last group.  The partial array
+// holds nblocks x width block partials followed by the groups' (nblocks + groups) x width
+// <= kRedPartialDoubles: up to kRedMaxBlocks blocks of kRedMaxWidth columns, or fewer
+// blocks of wider rows); the counter array one ticket per group and one for the groups.
+constexpr int kRedGroup = 256;
+constexpr int kRedMaxBlocks = 65536;
+constexpr int kRedMaxWidth = 16;
+constexpr int kRedGroups = kRedMaxBlocks / kRedGroup;
+constexpr size_t kRedPartialDoubles = (size_t)(kRedMaxBlocks + kRedGroups) * kRedMaxWidth;
+constexpr int kRedCounters = kRedGroups + 1;
+
 // Sites of one block when the hop stages each site's links in LDS.
 constexpr int kStageSites = 32;
 

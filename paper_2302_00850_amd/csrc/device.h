@@ -68,15 +68,23 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
     return (__umulhi(n, f.m) + n) >> f.s;
 }
 
-// Logical block index for an XCD-aware launch: workgroups are dispatched to the
-// 8 XCDs of the chip round-robin (block b runs on XCD b mod 8), so renumbering
-// b -> (b mod 8) * (grid / 8) + b / 8 (with the remainder spread over the first
-// XCDs) gives each XCD one contiguous range of the lattice, whose neighbour
-// spinors then stay in that XCD's own L2.  A permutation of [0, grid).
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t grid) {
-    const uint32_t q = grid >> 3, rem = grid & 7u;
+// XCD-aware work split.  Workgroups are dispatched to the 8 XCDs of the chip
+// round-robin (block b runs on XCD b mod 8), each with its own L2.  The nchunks chunks of
+// work are cut into one contiguous range per XCD, in proportion to its blocks, so the
+// neighbour spinors of a site stay in the L2 of the XCD that computes it.  Block b starts
+// at *first and steps by *step (its XCD's block count) up to *end; with G = nchunks every
+// block takes one chunk.  The trip count depends on b only.
+__device__ __forceinline__ void xcd_range(uint32_t b, uint32_t G, uint32_t nchunks,
+                                          uint32_t *first, uint32_t *end, uint32_t *step) {
+    const uint32_t q = G >> 3, rem = G & 7u;
     const uint32_t x = b & 7u, k = b >> 3;
-    return x * q + (x < rem ? x : rem) + k;
+    const uint32_t nbx = q + (x < rem ? 1u : 0u);
+    const uint32_t b0 = x * q + (x < rem ? x : rem);  // first logical block of XCD x
+    const uint32_t lo = (uint32_t)(((unsigned long long)nchunks * b0) / G);
+    const uint32_t hi = (uint32_t)(((unsigned long long)nchunks * (b0 + nbx)) / G);
+    *first = lo + k;
+    *end = hi;
+    *step = nbx;
 }
 
 // Coordinates of checkerboard site i of parity p.
@@ -796,12 +804,37 @@ __device__ __forceinline__ void clover_apply(const void *clov, int S, int p, uin
 
 // ---------------------------------------------------------------- reduction
 
-// Deterministic two-level sum of per-thread values.  The block's threads are
-// laid out as T "slots" (power of two) x `width` values; each thread passes
-// the values for columns q0 .. q0+n-1 of its slot.  Block sums go to
-// partial[blockIdx.x * width + q]; the last block to finish adds the partials
-// of all blocks in a fixed order into result[q] and re-arms the counter.
-// red must hold T * width doubles.
+// Per-block part of a two-kernel reduction: the lanes' values v[0..n) for columns q0..
+// of slot `slot` are summed over the block (LDS tree over the T slots of red, which holds
+// T * width doubles) into partial[bid][q].  A following reduce_partials launch adds the
+// blocks' partials in block order; the kernel boundary orders the writes, so blocks need
+// no fence or ticket (device-scope fences write back the XCD's L2 on this chip: with
+// tens of thousands of blocks they cost more than the hop).
+template <int NV>
+__device__ void block_sum_to_partial(double *red, int T, int width, int slot, int q0, int n,
+                                     const double (&v)[NV], double *partial, uint32_t bid) {
+    const int tid = threadIdx.x;
+    const int nt = blockDim.x;
+    for (int k = tid; k < T * width; k += nt) red[k] = 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k)  // constant indices keep v in registers
+        if (k < n) red[slot * width + q0 + k] = v[k];
+    __syncthreads();
+    for (int w = T >> 1; w > 0; w >>= 1) {
+        for (int k = tid; k < w * width; k += nt) red[k] += red[k + w * width];
+        __syncthreads();
+    }
+    for (int k = tid; k < width; k += nt) partial[(size_t)bid * width + k] = red[k];
+}
+
+// Deterministic per-block reduction: the lanes' values v[0..n) for columns q0.. of
+// slot `slot` are summed over the block (LDS tree over the T slots of red, which holds
+// T * width doubles) into partial[bid][q].  The last block of each group of kRedGroup
+// blocks (atomic ticket) adds its group's partials in block order; the last group to
+// finish adds the group sums in group order into result[q].  Every sum has a fixed
+// order whatever the timing, and each stage adds at most kRedGroup terms per column.
+// The tickets are re-armed to zero.
 template <int NV>
 __device__ void block_sum_to_result(double *red, int T, int width, int slot, int q0, int n,
                                     const double (&v)[NV], double *partial, unsigned *counter,
@@ -819,35 +852,60 @@ __device__ void block_sum_to_result(double *red, int T, int width, int slot, int
         __syncthreads();
     }
     for (int k = tid; k < width; k += nt) partial[(size_t)bid * width + k] = red[k];
+
+    const uint32_t group = bid / (uint32_t)kRedGroup;
+    const uint32_t ngroups = (nblocks + kRedGroup - 1) / (uint32_t)kRedGroup;
+    const uint32_t gfirst = group * (uint32_t)kRedGroup;
+    const uint32_t gsize = min((uint32_t)kRedGroup, nblocks - gfirst);
+    double *gpart = partial + (size_t)nblocks * width;  // group partials, after the blocks'
     __shared__ unsigned ticket;
+
+    // sum `count` rows of src (row stride width) starting at row `first` into red[0..width)
+    auto sum_rows = [&](const double *src, uint32_t first, uint32_t count) {
+        for (int k = tid; k < T * width; k += nt) {
+            const int s = k / width, q = k - s * width;
+            double a0 = 0.0, a1 = 0.0;
+            uint32_t b = (uint32_t)s;
+            for (; b + (uint32_t)T < count; b += 2u * T) {
+                a0 += src[(size_t)(first + b) * width + q];
+                a1 += src[(size_t)(first + b + T) * width + q];
+            }
+            for (; b < count; b += T) a0 += src[(size_t)(first + b) * width + q];
+            red[k] = a0 + a1;
+        }
+        __syncthreads();
+        for (int w = T >> 1; w > 0; w >>= 1) {
+            for (int k = tid; k < w * width; k += nt) red[k] += red[k + w * width];
+            __syncthreads();
+        }
+    };
+
+    __threadfence();
+    __syncthreads();
+    if (tid == 0)
+        ticket = __hip_atomic_fetch_add(counter + 1 + group, 1u, __ATOMIC_ACQ_REL,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (ticket != gsize - 1) return;
+    __threadfence();
+    // last block of the group: the group's partials in block order
+    sum_rows(partial, gfirst, gsize);
+    if (tid == 0) __hip_atomic_store(counter + 1 + group, 0u, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+    if (ngroups == 1) {
+        for (int k = tid; k < width; k += nt) result[k] = red[k];
+        return;
+    }
+    for (int k = tid; k < width; k += nt) gpart[(size_t)group * width + k] = red[k];
     __threadfence();
     __syncthreads();
     if (tid == 0)
         ticket = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    if (ticket != nblocks - 1) return;
+    if (ticket != ngroups - 1) return;
     __threadfence();
-    // last block: fixed-order sum over blocks, slot s handles blocks s, s+T, ...
-    // (four independent partial sums so the loads overlap)
-    const int nb = (int)nblocks;
-    for (int k = tid; k < T * width; k += nt) {
-        const int s = k / width, q = k - s * width;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int b = s;
-        for (; b + 3 * T < nb; b += 4 * T) {
-            a0 += partial[(size_t)b * width + q];
-            a1 += partial[(size_t)(b + T) * width + q];
-            a2 += partial[(size_t)(b + 2 * T) * width + q];
-            a3 += partial[(size_t)(b + 3 * T) * width + q];
-        }
-        for (; b < nb; b += T) a0 += partial[(size_t)b * width + q];
-        red[k] = (a0 + a1) + (a2 + a3);
-    }
-    __syncthreads();
-    for (int w = T >> 1; w > 0; w >>= 1) {
-        for (int k = tid; k < w * width; k += nt) red[k] += red[k + w * width];
-        __syncthreads();
-    }
+    // last group: the group sums in group order
+    sum_rows(gpart, 0, ngroups);
     for (int k = tid; k < width; k += nt) result[k] = red[k];
     if (tid == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -14,9 +14,8 @@
 
 namespace cola {
 
-constexpr int kMaxRhs = 16;
-constexpr int kMaxGrid = 65536;
-constexpr int kReduceGrid = 2048;  // most blocks of a launch that reduces
+constexpr int kMaxRhs = kRedMaxWidth;
+constexpr int kMaxGrid = kRedMaxBlocks;
 
 struct TuneEntry {
     int rpt = 1;
@@ -56,8 +55,8 @@ struct cola_handle {
     void *clov64 = nullptr, *clovinv64 = nullptr, *clov32 = nullptr, *clovinv32 = nullptr;
 
     // reductions
-    double *partial = nullptr;  // kMaxGrid * kMaxRhs
-    unsigned *counter = nullptr;
+    double *partial = nullptr;  // kRedPartialDoubles (block, then group partials)
+    unsigned *counter = nullptr;  // kRedCounters tickets, left at 0 between launches
     double *scal = nullptr;  // scalar arrays, kScalSlots * kMaxRhs
     int *active = nullptr;   // kMaxRhs
     double *host_scal = nullptr;  // pinned mirror of scal

@@ -17,8 +17,8 @@
 //   EPI_CLOV       out = C (D in)
 //   EPI_CLOV_XPAY  out = C x + a D in
 //   EPI_XPAY_CLOV  out = C (x + a D in)
-// and |out|^2 per rhs can be accumulated with a deterministic block +
-// last-block sum.
+// and |out|^2 per rhs can be accumulated: per-block partials, summed in block
+// order by a reduce_partials launch that follows.
 #pragma once
 
 #include "device.h"
@@ -132,16 +132,21 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
 #pragma unroll
     for (int r = 0; r < RPT; ++r) nrm[r] = 0.0;
 
-    const uint32_t stride = gridDim.x * blockDim.x;
-    const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+    // Work is cut into blockDim-lane chunks; each XCD (blocks are dispatched to the 8
+    // XCDs round-robin) takes one contiguous range of chunks, in proportion to its
+    // blocks, and its blocks stride over that range only: neighbouring sites stay in
+    // that XCD's L2 whether the grid covers the work once or loops over it.
+    uint32_t c0, c1, cstep, cfirst;
+    xcd_range(blockIdx.x, gridDim.x, (a.total + blockDim.x - 1) / blockDim.x, &c0, &c1, &cstep);
+    cfirst = c0;
     const uint32_t ncol = (uint32_t)g.s3;  // checkerboard sites of one timeslice
     // Lane w owns rhs group j of spatial column c in time chunk k and walks the chunk's
     // timeslices: the spinors its t-neighbours need were fetched one step earlier.  The
     // trip count is the same for every lane of a block (lanes past the end idle), so the
     // staging barriers are reached by all.
-    for (uint32_t base = lb * blockDim.x; base < a.total; base += stride)
+    for (uint32_t ch = cfirst; ch < c1; ch += cstep)
     for (int tt = 0; tt < a.tchunk; ++tt) {
-        const uint32_t w = base + threadIdx.x;
+        const uint32_t w = ch * blockDim.x + threadIdx.x;
         const bool valid = w < a.total;
         const uint32_t q = fdiv(w, a.div_groups);
         const uint32_t j = w - q * (uint32_t)a.groups;
@@ -242,8 +247,8 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     if (a.want_norm) {
         const int slot = threadIdx.x / a.groups;
         const int jj = threadIdx.x - slot * a.groups;
-        block_sum_to_result<RPT>(red, a.sites_per_block, a.nrhs, slot, jj * RPT, RPT, nrm,
-                                 a.partial, a.counter, a.result, blockIdx.x, gridDim.x);
+        block_sum_to_partial<RPT>(red, a.sites_per_block, a.nrhs, slot, jj * RPT, RPT, nrm,
+                                  a.partial, blockIdx.x);
     }
 }
 

@@ -16,6 +16,9 @@ struct Reduce {
 };
 
 // --- hop
+// result[q] = sum of partial[b][q] over b < nblocks in block order (width columns)
+hipError_t launch_reduce_partials(const double *partial, int nblocks, int width, double *result,
+                                  hipStream_t st);
 hipError_t launch_hop(const HopArgs &a, LinkFmt lf, int rpt, int grid, int block, hipStream_t st);
 
 // --- packing

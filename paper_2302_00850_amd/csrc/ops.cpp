@@ -189,8 +189,10 @@ TuneEntry default_entry(const Geom &g, int prec, int nrhs) {
     return t;
 }
 
+// One hop launch in shape te; with a norm, the partial-sum reduction follows unless
+// reduce is false (the caller then launches it, after its timing event).
 int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, const TuneEntry &te,
-                    hipStream_t st) {
+                    hipStream_t st, bool reduce = true, int *grid_out = nullptr) {
     HopArgs a;
     memset(&a, 0, sizeof a);
     a.g = h->g;
@@ -228,11 +230,9 @@ int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, cons
         a.div_ty = make_fastdiv((uint32_t)te.tile_y);
         a.div_nty = make_fastdiv((uint32_t)(g.L[1] / te.tile_y));
     }
-    // Launches that reduce keep the partial-sum array short, and explicit resident
-    // grids (te.grid < 0) ask for it: then the grid is the number of blocks the device
-    // holds at once (a grid-stride loop), so no block starts after others have done
-    // all their passes.
-    if (te.grid < 0 || (c.norm_result && grid > kReduceGrid)) {
+    // Resident grids (te.grid < 0): the number of blocks the device holds at once, the
+    // work in a grid-stride loop.
+    if (te.grid < 0) {
         char key[96];
         bool rph = true;
         for (int mu = 0; mu < 4; ++mu) rph &= h->phase[mu].y == 0.0;
@@ -248,11 +248,13 @@ int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, cons
             a.occupancy = nullptr;
             h->occupancy[key] = occ;
         }
-        long cap = (long)std::max(1, occ) * std::max(1, h->num_cu);
-        if (c.norm_result) cap = std::min<long>(cap, kReduceGrid);
+        const long cap = (long)std::max(1, occ) * std::max(1, h->num_cu);
         if (grid > cap) grid = (int)cap;
     }
     COLA_HIP(h, launch_hop(a, link_fmt(prec), te.rpt, grid, block, st));
+    if (grid_out) *grid_out = grid;
+    if (c.norm_result && reduce)
+        COLA_HIP(h, launch_reduce_partials(h->partial, grid, nrhs, c.norm_result, st));
     return COLA_OK;
 }
 
@@ -380,9 +382,12 @@ int hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, hipStream_t st) 
         if (!e0 || !e1) return set_error(h, COLA_EHIP, "hipEventCreate failed");
         COLA_HIP(h, hipEventRecord(e0, st));
     }
-    COLA_TRY(fill_and_launch(h, c, prec, nrhs, te, st));
+    int grid = 0;
+    COLA_TRY(fill_and_launch(h, c, prec, nrhs, te, st, false, &grid));
+    if (timed) COLA_HIP(h, hipEventRecord(e1, st));
+    if (c.norm_result)
+        COLA_HIP(h, launch_reduce_partials(h->partial, grid, nrhs, c.norm_result, st));
     if (timed) {
-        COLA_HIP(h, hipEventRecord(e1, st));
         double b, f;
         hop_work(h, prec, nrhs, c.epi, &b, &f);
         h->pending.push_back({e0, e1});
