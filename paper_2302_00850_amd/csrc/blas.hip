@@ -49,11 +49,13 @@ __global__ void __launch_bounds__(256) site_kernel(Fn f, const BlasShape sh, con
     if (red.result) {
         const int slot = threadIdx.x / sh.R;
         const int q = threadIdx.x - slot * sh.R;
-        block_sum_to_result<1>(lds, sh.T, sh.R, slot, q, 1, acc, red.partial, red.counter,
-                               red.result, blockIdx.y * gridDim.x + blockIdx.x,
-                               gridDim.x * gridDim.y);
+        block_sum_to_partial<1>(lds, sh.T, sh.R, slot, q, 1, acc, red.partial,
+                                blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     }
 }
+
+hipError_t launch_reduce(const double *partial, int nblocks, int width, double *result,
+                         hipStream_t st);
 
 template <class Fn>
 hipError_t run(const Fn &f, const BlasShape &sh, const Reduce *red, hipStream_t st) {
@@ -61,7 +63,10 @@ hipError_t run(const Fn &f, const BlasShape &sh, const Reduce *red, hipStream_t 
     const size_t shm = r.result ? (size_t)sh.T * sh.R * sizeof(double) : 0;
     hipLaunchKernelGGL(site_kernel<Fn>, dim3(sh.grid, sh.nblk), dim3(sh.T * sh.R), shm, st, f,
                        sh, r);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && r.result)
+        e = launch_reduce(r.partial, sh.grid * sh.nblk, sh.R, r.result, st);
+    return e;
 }
 
 template <SpinorFmt FX, SpinorFmt FP, SpinorFmt FR, SpinorFmt FA>
@@ -248,21 +253,21 @@ struct CloverFn {
 
 namespace {
 
-// result[q] = sum over b < nblocks of partial[b][q], in a fixed order: one block per
-// column, thread t adds blocks t, t + 256, ... and an LDS tree adds the threads.
+// result[q] = sum over b < nblocks of partial[q * nblocks + b], in a fixed order: one
+// block per column, thread t adds blocks t, t + 256, ... and an LDS tree adds the threads.
 __global__ void __launch_bounds__(256) reduce_partials_kernel(const double *partial,
-                                                              int nblocks, int width,
-                                                              double *result) {
+                                                              int nblocks, double *result) {
     __shared__ double red[256];
     const int q = blockIdx.x;
     const int t = threadIdx.x;
+    const double *col = partial + (size_t)q * nblocks;
     double a0 = 0.0, a1 = 0.0;
     int b = t;
     for (; b + 256 < nblocks; b += 512) {
-        a0 += partial[(size_t)b * width + q];
-        a1 += partial[(size_t)(b + 256) * width + q];
+        a0 += col[b];
+        a1 += col[b + 256];
     }
-    for (; b < nblocks; b += 256) a0 += partial[(size_t)b * width + q];
+    for (; b < nblocks; b += 256) a0 += col[b];
     red[t] = a0 + a1;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -276,10 +281,19 @@ __global__ void __launch_bounds__(256) reduce_partials_kernel(const double *part
 
 hipError_t launch_reduce_partials(const double *partial, int nblocks, int width, double *result,
                                   hipStream_t st) {
+    return launch_reduce(partial, nblocks, width, result, st);
+}
+
+namespace {
+
+hipError_t launch_reduce(const double *partial, int nblocks, int width, double *result,
+                         hipStream_t st) {
     hipLaunchKernelGGL(reduce_partials_kernel, dim3(width), dim3(256), 0, st, partial, nblocks,
-                       width, result);
+                       result);
     return hipGetLastError();
 }
+
+}  // namespace
 
 BlasShape blas_shape(const Geom &g, int nrhs, int nblk) {
     BlasShape b;
@@ -291,7 +305,9 @@ BlasShape blas_shape(const Geom &g, int nrhs, int nblk) {
     b.T = T;
     const size_t work = (size_t)g.S * nrhs;  // per parity block (grid row)
     size_t grid = (work + (size_t)T * nrhs - 1) / ((size_t)T * nrhs);
-    if (grid > 2048) grid = 2048;  // grid-stride; keeps the partial-sum array short
+    // at most kRedMaxBlocks blocks over all rows (the partial-sum array); grid-stride beyond
+    const size_t cap = (size_t)kRedMaxBlocks / (size_t)(nblk < 1 ? 1 : nblk);
+    if (grid > cap) grid = cap;
     b.grid = (int)(grid < 1 ? 1 : grid);
     return b;
 }

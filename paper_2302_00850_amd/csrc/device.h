@@ -806,13 +806,15 @@ __device__ __forceinline__ void clover_apply(const void *clov, int S, int p, uin
 
 // Per-block part of a two-kernel reduction: the lanes' values v[0..n) for columns q0..
 // of slot `slot` are summed over the block (LDS tree over the T slots of red, which holds
-// T * width doubles) into partial[bid][q].  A following reduce_partials launch adds the
-// blocks' partials in block order; the kernel boundary orders the writes, so blocks need
-// no fence or ticket (device-scope fences write back the XCD's L2 on this chip: with
-// tens of thousands of blocks they cost more than the hop).
+// T * width doubles) into partial[q * nblocks + bid] (column-major, so the reduction
+// reads each column contiguously).  A following reduce_partials launch adds the blocks'
+// partials in block order; the kernel boundary orders the writes, so blocks need no
+// fence or ticket (device-scope fences write back the XCD's L2 on this chip: with tens
+// of thousands of blocks they cost more than the kernel).
 template <int NV>
 __device__ void block_sum_to_partial(double *red, int T, int width, int slot, int q0, int n,
-                                     const double (&v)[NV], double *partial, uint32_t bid) {
+                                     const double (&v)[NV], double *partial, uint32_t bid,
+                                     uint32_t nblocks) {
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
     for (int k = tid; k < T * width; k += nt) red[k] = 0.0;
@@ -825,7 +827,7 @@ __device__ void block_sum_to_partial(double *red, int T, int width, int slot, in
         for (int k = tid; k < w * width; k += nt) red[k] += red[k + w * width];
         __syncthreads();
     }
-    for (int k = tid; k < width; k += nt) partial[(size_t)bid * width + k] = red[k];
+    for (int k = tid; k < width; k += nt) partial[(size_t)k * nblocks + bid] = red[k];
 }
 
 // Deterministic per-block reduction: the lanes' values v[0..n) for columns q0.. of

@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
         const int slot = threadIdx.x / a.groups;
         const int jj = threadIdx.x - slot * a.groups;
         block_sum_to_partial<RPT>(red, a.sites_per_block, a.nrhs, slot, jj * RPT, RPT, nrm,
-                                  a.partial, blockIdx.x);
+                                  a.partial, blockIdx.x, gridDim.x);
     }
 }
 
