@@ -254,23 +254,24 @@ struct CloverFn {
 namespace {
 
 // result[q] = sum over b < nblocks of partial[q * nblocks + b], in a fixed order: one
-// block per column, thread t adds blocks t, t + 256, ... and an LDS tree adds the threads.
-__global__ void __launch_bounds__(256) reduce_partials_kernel(const double *partial,
-                                                              int nblocks, double *result) {
-    __shared__ double red[256];
+// block of 1024 threads per column; thread t adds blocks t + 1024 k in eight independent
+// chains (the loads overlap), then an LDS tree adds the threads.
+__global__ void __launch_bounds__(1024) reduce_partials_kernel(const double *partial,
+                                                               int nblocks, double *result) {
+    __shared__ double red[1024];
     const int q = blockIdx.x;
     const int t = threadIdx.x;
     const double *col = partial + (size_t)q * nblocks;
-    double a0 = 0.0, a1 = 0.0;
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int b = t;
-    for (; b + 256 < nblocks; b += 512) {
-        a0 += col[b];
-        a1 += col[b + 256];
+    for (; b + 7 * 1024 < nblocks; b += 8 * 1024) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a[k] += col[b + k * 1024];
     }
-    for (; b < nblocks; b += 256) a0 += col[b];
-    red[t] = a0 + a1;
+    for (; b < nblocks; b += 1024) a[0] += col[b];
+    red[t] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = 512; w > 0; w >>= 1) {
         if (t < w) red[t] += red[t + w];
         __syncthreads();
     }
@@ -288,7 +289,7 @@ namespace {
 
 hipError_t launch_reduce(const double *partial, int nblocks, int width, double *result,
                          hipStream_t st) {
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(width), dim3(256), 0, st, partial, nblocks,
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(width), dim3(1024), 0, st, partial, nblocks,
                        result);
     return hipGetLastError();
 }
