@@ -158,8 +158,9 @@ TuneEntry default_entry(const Geom &g, int prec, int nrhs) {
     t.grid = 0;
     t.tchunk = default_tchunk(g, G);
     // Spatial tiles for the multi-rhs FP16 / FP32 hops, where they measured fastest on a
-    // 32^3 x 64 lattice (16x8 (y, z) columns walked through t).  Lattices the tile does
-    // not divide, and single-rhs hops, keep the time-chunk order.
+    // 32^3 x 64 lattice: (y, z) tiles of 16x8 columns walked through t (8x8 and 8x4
+    // tiles come within run-to-run noise).  Lattices the tile does not divide, and
+    // single-rhs hops, keep the time-chunk order.
     int ty = 0, tz = 0;
     if (nrhs >= 4 && (prec == COLA_FP16 || prec == COLA_FP32)) ty = 16, tz = 8;
     if (ty > 0 && tile_ok(g, ty, tz)) {
