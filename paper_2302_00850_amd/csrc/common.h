@@ -69,7 +69,7 @@ struct HopArgs {
     int groups;      // R / rhs-per-thread
     FastDiv div_groups;
     int epi;         // Epilogue
-    int want_norm;   // accumulate |out|^2 per rhs into `result`
+    int want_norm;   // per-block partials of |out|^2 per rhs into `partial`
     double a;        // epilogue coefficient
     Cplx64 phase[4]; // boundary phases e^{i theta_mu}
     const void *in;      // parity (1 - parity) block
@@ -77,9 +77,7 @@ struct HopArgs {
     const void *x;       // parity `parity` block (epilogues 1, 3, 4)
     const void *gauge;   // packed gauge buffer of the launch precision
     const void *clov;    // packed clover buffer (both parities) for epilogues 2-4
-    double *partial;     // per-block partial sums [grid][R]
-    unsigned *counter;   // last-block ticket, left at 0
-    double *result;      // [R]
+    double *partial;     // per-block |out|^2 partials [R][grid] (want_norm)
     uint32_t total;      // (Lt / tchunk) * (Vh / Lt) * groups lanes of work
     int sites_per_block; // T: threads per block = T * groups
     int tchunk;          // timeslices one lane walks (t-streaming); divides Lt
@@ -96,11 +94,12 @@ struct HopArgs {
     int *occupancy;
 };
 
-// Deterministic reductions: per-block partials are summed per group of kRedGroup blocks
-// by the group's last block, then the group sums by the last group.  The partial array
-// holds nblocks x width block partials followed by the groups' (nblocks + groups) x width
-// <= kRedPartialDoubles: up to kRedMaxBlocks blocks of kRedMaxWidth columns, or fewer
-// blocks of wider rows); the counter array one ticket per group and one for the groups.
+// Deterministic reductions.  Kernels write per-block partial sums, column-major
+// (partial[q * nblocks + b], at most kRedMaxBlocks blocks of kRedMaxWidth columns), and a
+// reduce launch adds them in block order.  The block-CG Gram kernel (few blocks, wide
+// rows) instead sums per group of kRedGroup blocks with atomic tickets, then over the
+// groups; its block rows and group rows fit the same array, and the counter array holds
+// one ticket per group and one for the groups.
 constexpr int kRedGroup = 256;
 constexpr int kRedMaxBlocks = 65536;
 constexpr int kRedMaxWidth = 16;

@@ -214,8 +214,6 @@ int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, cons
     a.gauge = h->gauge[(int)link_fmt(prec)];
     a.clov = c.clov;
     a.partial = h->partial;
-    a.counter = h->counter;
-    a.result = c.norm_result;
     a.total = (uint32_t)(h->g.Vh / te.tchunk) * (uint32_t)groups;
     a.sites_per_block = T;
     a.tchunk = te.tchunk;
