@@ -101,7 +101,8 @@ def hop_mode(args):
     from paper_2302_00850_amd.synth import Synth, bc_phases
 
     dims = tuple(int(v) for v in args.lattice.split(","))
-    s = Synth(0, device="cuda")
+    # numpy draws on the host for small lattices; the device generator beyond 4M sites
+    s = Synth(0, device="cuda", rng="torch" if np.prod(dims) > 4 * 2**20 else "numpy")
     U = s.gauge(dims)
     bc = bc_phases((0, 0, 0, np.pi))
     for prec in [int(p) for p in args.prec.split(",")]:

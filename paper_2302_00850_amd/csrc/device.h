@@ -319,9 +319,10 @@ struct SpinorBlock {
     }
 
     // FP16 only: store N consecutive right-hand sides of site i (as load_raw_h2_group);
-    // v is replaced by the values actually stored.
+    // with keep, v is replaced by the values actually stored.
     template <int N>
-    __device__ __forceinline__ void store_group(uint32_t i, uint32_t r0, cpx<float> v[N][12]) const {
+    __device__ __forceinline__ void store_group(uint32_t i, uint32_t r0, cpx<float> v[N][12],
+                                                bool keep) const {
         static_assert(F == SpinorFmt::F16, "grouped stores are for FP16 blocks");
         struct G { half2s x[N]; };
         struct FS { float x[N]; };
@@ -339,7 +340,7 @@ struct SpinorBlock {
             for (int c = 0; c < 12; ++c) {
                 const half2s h = to_half2(v[r][c].x * inv, v[r][c].y * inv);
                 w[c].x[r] = h;
-                v[r][c] = {m * (float)h.x, m * (float)h.y};
+                if (keep) v[r][c] = {m * (float)h.x, m * (float)h.y};
             }
             f.x[r] = m;
         }

@@ -233,7 +233,8 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
         }
         // FP16: one wide store per component for the lane's RPT right-hand sides;
         // acc then holds the stored (rounded) values
-        if constexpr (SF == SpinorFmt::F16) out.template store_group<RPT>(i, j * RPT, acc);
+        if constexpr (SF == SpinorFmt::F16)
+            out.template store_group<RPT>(i, j * RPT, acc, a.want_norm != 0);
         if (a.want_norm) {
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {

@@ -240,6 +240,25 @@ def test_staged_links_identical(fields, prec, op, monkeypatch):
         assert rel(np.where(_even(DIMS), got, 0), want) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", [2, 3])
+@pytest.mark.parametrize("nrhs", [5, 8, 16])
+def test_hop_rhs_counts(fields, prec, nrhs):
+    """Right-hand-side counts with partial wavefronts (5), the smallest staged count (8)
+    and the largest (16), against the oracle."""
+    U, psi0 = fields
+    s = Synth(202)
+    psi = s.gaussian_spinor(DIMS, nrhs).numpy()
+    lat = _lat(U, GENERIC)
+    src = np.where(~_even(DIMS), psi, 0)
+    pin = lat.pack(_cuda(src), prec, 1)
+    out = lat.empty_packed(prec, nrhs, 0)
+    lat.dslash(out, pin, cola.COLA_OP_HOP, 0, prec, nrhs)
+    got = np.where(_even(DIMS), lat.unpack(out, prec, nrhs, 0).cpu().numpy(), 0)
+    src_r = np.where(~_even(DIMS), lat.unpack(pin, prec, nrhs, 1).cpu().numpy(), 0)
+    want = np.where(_even(DIMS), oracle.hop(U, src_r, GENERIC), 0)
+    assert rel(got, want) <= TOL[prec]
+
+
 def test_hop_deterministic_and_timing_stats(fields):
     U, psi = fields
     lat = _lat(U, ANTI, flags=cola.COLA_FLAG_TIMING)
