@@ -208,8 +208,13 @@ int cola_fermion_force(cola_handle_t *h, void *F_dev, const void *X_dev, const v
 int cola_get_stats(cola_handle_t *h, cola_stats_t *s); /* synchronises pending timings */
 int cola_reset_stats(cola_handle_t *h);
 
-/* Autotuning of the hop launch shape (threads per block, rhs per thread, grid).
- * mode 0: off (defaults), 1: tune on first use of a key, 2: re-tune every key.
+/* Autotuning of the hop launch shape (the paper's remark that performance hinges on
+ * how lattice sites map to GPU threads, in its paragraph on the GPU execution model):
+ * sites per block, rhs per thread, grid (natural or resident), time chunk, spatial tile
+ * and LDS staging of the site's links.  Every shape gives bitwise the same result.
+ * Keys are (lattice, precision, nrhs, epilogue, fused norm).
+ * mode 0: off (defaults), 1: tune on first use of a key (each candidate timed on the
+ * caller's buffers, so that first call takes longer), 2: re-tune every key.
  * The table is kept per handle; cola_tune_dump writes it as JSON text into buf
  * (returns the length needed, including the terminating NUL). */
 int cola_set_tuning(cola_handle_t *h, int mode);

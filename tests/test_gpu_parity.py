@@ -214,14 +214,16 @@ STAGED = ["1,16,0,1,0,0,1", "1,16,0,1,2,2,1", "1,8,7,1,0,0,1", "1,16,3,2,0,0,1",
 
 
 @pytest.mark.parametrize("prec", [2, 3])
-@pytest.mark.parametrize("op", ["hop", "schur"])
+@pytest.mark.parametrize("op", ["hop", "schur", "clover_schur"])
 def test_staged_links_identical(fields, prec, op, monkeypatch):
     """With 12 rhs the lanes of a site can stage its links in LDS; the result is bitwise
     the one of per-lane link loads, for several block sizes, grid-stride loops with a
-    ragged last pass, time chunks and tiles (and with the fused norm of the Schur op)."""
+    ragged last pass, time chunks and tiles (and with the fused norm and clover
+    epilogues of the Schur operator)."""
     U, psi = fields
     nrhs = 12
-    lat = _lat(U, GENERIC)
+    clover = op == "clover_schur"
+    lat = _lat(U, GENERIC, csw=1.0 if clover else 0.0, kappa=0.118 if clover else KAPPA)
     code = cola.COLA_OP_HOP if op == "hop" else cola.COLA_OP_SCHUR
     pin = lat.pack(_cuda(psi), prec, 1 if op == "hop" else 0)
     monkeypatch.setenv("COLA_HOP_SHAPE", "1,16,0,1,0,0,0")
