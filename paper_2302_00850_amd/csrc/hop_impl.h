@@ -21,21 +21,55 @@
 // order by a reduce_partials launch that follows.
 #pragma once
 
+#include <type_traits>
+
 #include "device.h"
 #include "launch.h"
 
 namespace cola {
 
+// The neighbour spinor of one direction as loaded: raw halves and site scales for FP16,
+// compute-precision components otherwise; n is the neighbour's checkerboard index.
+template <SpinorFmt SF, int RPT>
+struct Fetched {
+    using T = typename SpinorT<SF>::real;
+    using E = typename std::conditional<SF == SpinorFmt::F16, h2, cpx<T>>::type;
+    E s[RPT][12];
+    float scl[RPT];
+    uint32_t n;
+};
+
+// Issue the loads of direction (MU, DIR)'s neighbour spinor.  The kernel fetches one
+// direction ahead of the one it computes, so a wavefront always has a direction's
+// loads in flight while it does arithmetic (the register fences between directions are
+// scheduling barriers: without this the loads of a direction would only start after
+// the previous direction finished).
+template <int MU, int DIR, SpinorFmt SF, int RPT>
+__device__ __forceinline__ void hop_fetch(const HopArgs &a, const SpinorBlock<SF, true> &in,
+                                          uint32_t i, const int x[4], uint32_t j,
+                                          Fetched<SF, RPT> &f) {
+    const Geom &g = a.g;
+    f.n = DIR == 0 ? nb_fwd(g, i, x, MU) : nb_bwd(g, i, x, MU);
+    if constexpr (SF == SpinorFmt::F16) {
+        in.template load_raw_h2_group<RPT>(f.n, j * RPT, f.s, f.scl);
+    } else {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            typename SpinorT<SF>::real one;  // the site scale, 1 for FP32 and FP64 blocks
+            in.load_unscaled(f.n, j * RPT + r, f.s[r], &one);
+        }
+    }
+}
+
 // One of the eight hopping directions (MU, DIR) added into the accumulators of the
-// lane's RPT right-hand sides at checkerboard site i (coordinates x).  A template, so
-// the eight directions are unrolled by construction and every spin-projection branch
-// resolves at compile time.
+// lane's RPT right-hand sides at checkerboard site i (coordinates x), from the fetched
+// neighbour spinor.  A template, so the eight directions are unrolled by construction
+// and every spin-projection branch resolves at compile time.
 template <int MU, int DIR, SpinorFmt SF, LinkFmt LF, int RPT, bool RPH, bool SHL>
-__device__ __forceinline__ void hop_dir(const HopArgs &a, const SpinorBlock<SF, true> &in, int p,
-                                        uint32_t i, const int x[4], uint32_t j,
+__device__ __forceinline__ void hop_dir(const HopArgs &a, int p, uint32_t i, const int x[4],
                                         typename SpinorT<SF>::real sg_f,
                                         cpx<typename SpinorT<SF>::real> acc[RPT][12],
-                                        const uint32_t *staged) {
+                                        const uint32_t *staged, const Fetched<SF, RPT> &f) {
     using T = typename SpinorT<SF>::real;
     using C = cpx<T>;
     const Geom &g = a.g;
@@ -43,7 +77,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs &a, const SpinorBlock<SF, 
     const T sg_b = -sg_f;
     // dir 0: (1 + sg_f g_mu) e+ U_mu(x) psi(x+mu)
     // dir 1: (1 + sg_b g_mu) e- U_mu(x-mu)^H psi(x-mu)
-    const uint32_t n = dir == 0 ? nb_fwd(g, i, x, mu) : nb_bwd(g, i, x, mu);
+    const uint32_t n = f.n;
     const T sg = dir == 0 ? sg_f : sg_b;
     const bool bnd = dir == 0 ? x[mu] == g.L[mu] - 1 : x[mu] == 0;
     T eta = (T)1;
@@ -64,21 +98,18 @@ __device__ __forceinline__ void hop_dir(const HopArgs &a, const SpinorBlock<SF, 
             read_staged(staged + (2 * MU + DIR) * kStageWords, L);
         else
             load_link_h2<dir == 1>(a.gauge, g.S, dir == 0 ? p : 1 - p, mu, dir == 0 ? i : n, L);
-        h2 s[RPT][12];
-        float scl[RPT];
-        in.template load_raw_h2_group<RPT>(n, j * RPT, s, scl);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             h2 hh[6];
             C w[6];
-            project_h2(mu, (_Float16)sg, s[r], hh);
+            project_h2(mu, (_Float16)sg, f.s[r], hh);
             mul_h2(L, hh, w);
             mul_h2(L, hh + 3, w + 3);
             if constexpr (!RPH) {
 #pragma unroll
                 for (int k = 0; k < 6; ++k) w[k] = cmul(ph, w[k]);
             }
-            expand_add(mu, sg, w, acc[r], eta * scl[r]);
+            expand_add(mu, sg, w, acc[r], eta * f.scl[r]);
         }
     } else {
         C u[3][3];
@@ -88,10 +119,8 @@ __device__ __forceinline__ void hop_dir(const HopArgs &a, const SpinorBlock<SF, 
             load_link<LF, T>(a.gauge, g.S, dir == 0 ? p : 1 - p, mu, dir == 0 ? i : n, u);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            C s[12], h[6], w[6];
-            T one;  // the site scale, 1 for FP32 and FP64 blocks
-            in.load_unscaled(n, j * RPT + r, s, &one);
-            project(mu, sg, s, h);
+            C h[6], w[6];
+            project(mu, sg, f.s[r], h);
             if constexpr (dir == 0) {
                 su3_mul(u, h, w);
                 su3_mul(u, h + 3, w + 3);
@@ -173,14 +202,15 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
         site_coords(g, i, p, x);
         const uint32_t *staged = nullptr;
         if constexpr (SHL) {
-            // block = sites_per_block sites x groups lanes (groups >= 8), whole sites
+            // block = sites_per_block sites x groups lanes, whole sites; lane j stages links
+            // j, j + groups, ... (link d: mu = d / 2, backward for odd d)
             const uint32_t slot = threadIdx.x / (uint32_t)a.groups;
             uint32_t *mine = stage + slot * kStageSite;
             __syncthreads();  // the previous site's links are no longer read
-            if (valid && j < 8) {
-                const int mu = (int)(j >> 1);
+            for (uint32_t d = j; valid && d < 8; d += (uint32_t)a.groups) {
+                const int mu = (int)(d >> 1);
                 const uint32_t n = nb_bwd_rt(g, i, x, mu);
-                stage_link<LF>(a.gauge, g.S, p, mu, (j & 1) != 0, i, n, mine + j * kStageWords);
+                stage_link<LF>(a.gauge, g.S, p, mu, (d & 1) != 0, i, n, mine + d * kStageWords);
             }
             __syncthreads();
             staged = mine;
@@ -192,14 +222,24 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) acc[r][c] = {(T)0, (T)0};
 
-        hop_dir<0, 0, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
-        hop_dir<0, 1, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
-        hop_dir<1, 0, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
-        hop_dir<1, 1, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
-        hop_dir<2, 0, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
-        hop_dir<2, 1, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
-        hop_dir<3, 0, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
-        hop_dir<3, 1, SF, LF, RPT, RPH, SHL>(a, in, p, i, x, j, sg_f, acc, staged);
+        // directions computed one behind their fetch (two buffers, A and B)
+        Fetched<SF, RPT> fa, fb;
+        hop_fetch<0, 0, SF, RPT>(a, in, i, x, j, fa);
+        hop_fetch<0, 1, SF, RPT>(a, in, i, x, j, fb);
+        hop_dir<0, 0, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fa);
+        hop_fetch<1, 0, SF, RPT>(a, in, i, x, j, fa);
+        hop_dir<0, 1, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fb);
+        hop_fetch<1, 1, SF, RPT>(a, in, i, x, j, fb);
+        hop_dir<1, 0, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fa);
+        hop_fetch<2, 0, SF, RPT>(a, in, i, x, j, fa);
+        hop_dir<1, 1, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fb);
+        hop_fetch<2, 1, SF, RPT>(a, in, i, x, j, fb);
+        hop_dir<2, 0, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fa);
+        hop_fetch<3, 0, SF, RPT>(a, in, i, x, j, fa);
+        hop_dir<2, 1, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fb);
+        hop_fetch<3, 1, SF, RPT>(a, in, i, x, j, fb);
+        hop_dir<3, 0, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fa);
+        hop_dir<3, 1, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fb);
 
         const T ca = (T)a.a;
 #pragma unroll
@@ -284,12 +324,17 @@ hipError_t hop_launch_fmt(const HopArgs &a, int rpt, int grid, int block, hipStr
     for (int mu = 0; mu < 4; ++mu) real_phase &= a.phase[mu].y == 0.0;
     // several rhs per lane only where the accumulators fit (FP64 keeps one)
     constexpr bool multi = SF != SpinorFmt::F64;
-    // links staged in LDS by the site's lanes: 12-real FP16 / FP32 links, one rhs per lane
+    // links staged in LDS by the site's lanes: 12-real FP16 / FP32 links, one or two rhs
+    // per lane
     constexpr bool stageable = LF == LinkFmt::F16_12 || LF == LinkFmt::F32_12;
     if constexpr (stageable) {
         if (a.stage_links && rpt == 1) {
             if (real_phase) return hop_launch_epi<SF, LF, CR, 1, true, true>(a, grid, block, st);
             return hop_launch_epi<SF, LF, CR, 1, false, true>(a, grid, block, st);
+        }
+        if (a.stage_links && rpt == 2) {
+            if (real_phase) return hop_launch_epi<SF, LF, CR, 2, true, true>(a, grid, block, st);
+            return hop_launch_epi<SF, LF, CR, 2, false, true>(a, grid, block, st);
         }
     }
     if (a.stage_links) return hipErrorInvalidValue;

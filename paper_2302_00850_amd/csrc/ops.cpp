@@ -139,13 +139,14 @@ bool tile_ok(const Geom &g, int ty, int tz) {
     return ty > 0 && tz > 0 && g.L[1] % ty == 0 && g.L[2] % tz == 0;
 }
 
-// Link staging needs eight lanes per site (one rhs each), whole sites of at most
-// kStageSites per block, a 12-real FP16 or FP32 field and a packed field addressable
-// with 32-bit byte offsets.
+// Link staging: one or two rhs per lane, at least three lanes per site to share the
+// eight links, whole sites of at most kStageSites per block, a 12-real FP16 or FP32 field
+// and a packed field addressable with 32-bit byte offsets.
 bool stage_ok(const Geom &g, int prec, int nrhs, const TuneEntry &t) {
     if (prec != COLA_FP16 && prec != COLA_FP32) return false;
     const double bytes = 8.0 * 3 * g.S * (prec == COLA_FP16 ? 8 : 16);
-    return t.rpt == 1 && nrhs >= 8 && t.sites_per_block <= kStageSites && bytes < 2147483648.0;
+    return (t.rpt == 1 || t.rpt == 2) && nrhs / t.rpt >= 3 && t.sites_per_block <= kStageSites &&
+           bytes < 2147483648.0;
 }
 
 TuneEntry default_entry(const Geom &g, int prec, int nrhs) {
@@ -158,17 +159,19 @@ TuneEntry default_entry(const Geom &g, int prec, int nrhs) {
     t.grid = 0;
     t.tchunk = default_tchunk(g, G);
     // Spatial tiles for the multi-rhs FP16 / FP32 hops, where they measured fastest on a
-    // 32^3 x 64 lattice: (y, z) tiles of 16x8 columns walked through t (8x8 and 8x4
-    // tiles come within run-to-run noise).  Lattices the tile does not divide, and
-    // single-rhs hops, keep the time-chunk order.
+    // 32^3 x 64 lattice: (y, z) tiles of 8x8 (FP16; fastest in three of four runs on
+    // different boxes, and the fewest L2 read misses) and 16x8 (FP32) columns walked
+    // through t.  Lattices the tile does not divide, and single-rhs hops, keep the
+    // time-chunk order.
     int ty = 0, tz = 0;
-    if (nrhs >= 4 && (prec == COLA_FP16 || prec == COLA_FP32)) ty = 16, tz = 8;
+    if (nrhs >= 4 && prec == COLA_FP16) ty = 8, tz = 8;
+    if (nrhs >= 4 && prec == COLA_FP32) ty = 16, tz = 8;
     if (ty > 0 && tile_ok(g, ty, tz)) {
         t.tile_y = ty;
         t.tile_z = tz;
         t.tchunk = 1;
     }
-    t.stage = stage_ok(g, prec, nrhs, t) ? 1 : 0;
+    t.stage = nrhs >= 8 && stage_ok(g, prec, nrhs, t) ? 1 : 0;
     // Measurement knob: COLA_HOP_SHAPE="rpt,sites_per_block,grid,tchunk" pins the
     // untuned launch shape (ignored unless every field is valid for this launch).
     if (const char *env = getenv("COLA_HOP_SHAPE")) {

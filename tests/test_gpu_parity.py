@@ -210,7 +210,8 @@ def test_hop_identical_across_launch_shapes(fields, prec, monkeypatch):
 
 
 STAGED = ["1,16,0,1,0,0,1", "1,16,0,1,2,2,1", "1,8,7,1,0,0,1", "1,16,3,2,0,0,1",
-          "1,16,0,5,0,0,1", "1,32,0,1,2,4,1", "1,16,-1,1,2,2,1"]
+          "1,16,0,5,0,0,1", "1,32,0,1,2,4,1", "1,16,-1,1,2,2,1", "2,32,0,1,0,0,1",
+          "2,16,5,1,2,2,1", "2,32,0,2,0,0,1"]
 
 
 @pytest.mark.parametrize("prec", [2, 3])
