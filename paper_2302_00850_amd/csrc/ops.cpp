@@ -161,11 +161,12 @@ TuneEntry default_entry(const Geom &g, int prec, int nrhs) {
     // Spatial tiles for the multi-rhs FP16 / FP32 hops, where they measured fastest on a
     // 32^3 x 64 lattice: (y, z) tiles of 8x8 (FP16; fastest in three of four runs on
     // different boxes, and the fewest L2 read misses) and 16x8 (FP32) columns walked
-    // through t.  Lattices the tile does not divide, and single-rhs hops, keep the
-    // time-chunk order.
+    // through t; 4x8 for multi-rhs FP64 (the outer residuals of the mixed solvers).
+    // Lattices the tile does not divide, and single-rhs hops, keep the time-chunk order.
     int ty = 0, tz = 0;
     if (nrhs >= 4 && prec == COLA_FP16) ty = 8, tz = 8;
     if (nrhs >= 4 && prec == COLA_FP32) ty = 16, tz = 8;
+    if (nrhs >= 4 && (prec == COLA_FP64 || prec == COLA_FP64_12)) ty = 4, tz = 8;  // tuner's pick
     if (ty > 0 && tile_ok(g, ty, tz)) {
         t.tile_y = ty;
         t.tile_z = tz;

@@ -142,6 +142,7 @@ struct Outcome {
     int iterations = 0;
     int outer = 0;
     int reliable = 0;
+    std::vector<double> final_tr;  // true |r|^2 of the returned x, when the solver has it
 };
 
 // ---------------------------------------------------------------- FP64 / FP32 reliable
@@ -186,7 +187,10 @@ int solve_reliable(const Ctx &c, int sloppy_prec, const cola_cg_params_t &p, voi
         act[q] = tr[q] > thr[q];
         all_done &= !act[q];
     }
-    if (all_done) return COLA_OK;
+    if (all_done) {
+        o->final_tr = tr;
+        return COLA_OK;
+    }
     COLA_TRY(write_active(c, act));
     const Reduce red_rho = reduce_into(h, RHO);
     if (!same) COLA_HIP(h, launch_convert(sh, fs, SpinorFmt::F64, rs, r64, nullptr, 0, &red_rho, c.st));
@@ -233,6 +237,7 @@ int solve_reliable(const Ctx &c, int sloppy_prec, const cola_cg_params_t &p, voi
                 }
                 if (done) {
                     stop = true;
+                    o->final_tr = tr;  // x64 holds the whole solution (xs was folded in)
                 } else {
                     if (!same)
                         COLA_HIP(h, launch_convert(sh, fs, SpinorFmt::F64, rs, r64, nullptr, 0,
@@ -268,6 +273,7 @@ int solve_reliable(const Ctx &c, int sloppy_prec, const cola_cg_params_t &p, voi
         COLA_TRY(read_slot(c, TRUE_RES, tr.data()));
         for (int q = 0; q < c.R; ++q)
             if (tr[q] > thr[q]) o->status = COLA_NOT_CONVERGED;
+        o->final_tr = tr;
     }
     return COLA_OK;
 }
@@ -489,7 +495,10 @@ int solve_defect(const Ctx &c, int inner_prec, const cola_cg_params_t &p, void *
             s[q] = std::sqrt(tr[q]);
             if (act[q] && prev[q] > 0) worst = std::max(worst, std::sqrt(tr[q] / prev[q]));
         }
-        if (done) return COLA_OK;
+        if (done) {
+            o->final_tr = tr;
+            return COLA_OK;
+        }
         if (o->iterations >= p.max_iter) {
             o->status = COLA_NOT_CONVERGED;
             return COLA_OK;
@@ -610,12 +619,17 @@ int cg_solve_impl(cola_handle_t *h, void *x, const void *b, int nrhs, const cola
         default: return set_error(h, COLA_EINVAL, "unknown solver scheme");
     }
 
-    // final FP64 true residual of the solved system
-    void *r64;
-    COLA_TRY(vec(c, "r64", SpinorFmt::F64, &r64));
-    COLA_TRY(true_residual(c, r64, b64, x64, TRUE_RES));
+    // final FP64 true residual of the solved system (the solver's last one when it
+    // computed it for the returned x)
     std::vector<double> tr(nrhs);
-    COLA_TRY(read_slot(c, TRUE_RES, tr.data()));
+    if ((int)o.final_tr.size() == nrhs) {
+        tr = o.final_tr;
+    } else {
+        void *r64;
+        COLA_TRY(vec(c, "r64", SpinorFmt::F64, &r64));
+        COLA_TRY(true_residual(c, r64, b64, x64, TRUE_RES));
+        COLA_TRY(read_slot(c, TRUE_RES, tr.data()));
+    }
     for (int q = 0; q < nrhs; ++q)
         if (!(tr[q] <= thr[q]) && o.status == COLA_OK) o.status = COLA_NOT_CONVERGED;
 
