@@ -102,49 +102,61 @@ __global__ void pack_gauge_kernel(const Geom g, const cpx<double> *__restrict__ 
         atomicMax(maxdev, (unsigned long long)__double_as_longlong(red[0]));
 }
 
+// One lane per (parity block, checkerboard site, rhs), rhs fastest: the packed side
+// (rhs innermost) is written in contiguous runs, and each lane reads its site's 192
+// canonical bytes in order.  Only the sites of the packed parities are visited.
 template <SpinorFmt F>
 __global__ void pack_spinor_kernel(const Geom g, void *dst, const cpx<double> *__restrict__ src,
                                    int nrhs, int parity, size_t block_bytes) {
     using R = typename SpinorT<F>::real;
     const uint32_t V = 2u * (uint32_t)g.Vh;
-    const uint32_t total = V * (uint32_t)nrhs;
+    const uint32_t per = (uint32_t)g.Vh * (uint32_t)nrhs;  // lanes per parity block
+    const uint32_t total = (parity >= 0 ? 1u : 2u) * per;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += gridDim.x * blockDim.x) {
-        const uint32_t r = t / V;
-        const uint32_t s = t - r * V;
+        const uint32_t blk = t / per;
+        const uint32_t e = t - blk * per;
+        const uint32_t i = e / (uint32_t)nrhs;
+        const uint32_t r = e - i * (uint32_t)nrhs;
+        const int p = parity >= 0 ? parity : (int)blk;
         int x[4];
-        lex_coords(g, s, x);
-        const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
-        if (parity >= 0 && p != parity) continue;
-        const int blk = parity >= 0 ? 0 : p;
+        site_coords(g, i, p, x);
+        const uint32_t s = (uint32_t)x[0] +
+                           (uint32_t)g.L[0] * ((uint32_t)x[1] + (uint32_t)g.L[1] *
+                                               ((uint32_t)x[2] + (uint32_t)g.L[2] * (uint32_t)x[3]));
         const SpinorBlock<F> out((char *)dst + blk * block_bytes, g.S, nrhs);
         cpx<R> v[12];
-        const cpx<double> *in = src + (size_t)t * 12;
+        const cpx<double> *in = src + ((size_t)r * V + s) * 12;
 #pragma unroll
         for (int c = 0; c < 12; ++c) v[c] = {(R)in[c].x, (R)in[c].y};
-        out.store(s >> 1, r, v);
+        out.store(i, r, v);
     }
 }
 
+// The inverse of pack_spinor_kernel; sites of the other parity are left untouched.
 template <SpinorFmt F>
 __global__ void unpack_spinor_kernel(const Geom g, cpx<double> *__restrict__ dst,
                                      const void *src, int nrhs, int parity, size_t block_bytes) {
     using R = typename SpinorT<F>::real;
     const uint32_t V = 2u * (uint32_t)g.Vh;
-    const uint32_t total = V * (uint32_t)nrhs;
+    const uint32_t per = (uint32_t)g.Vh * (uint32_t)nrhs;
+    const uint32_t total = (parity >= 0 ? 1u : 2u) * per;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += gridDim.x * blockDim.x) {
-        const uint32_t r = t / V;
-        const uint32_t s = t - r * V;
+        const uint32_t blk = t / per;
+        const uint32_t e = t - blk * per;
+        const uint32_t i = e / (uint32_t)nrhs;
+        const uint32_t r = e - i * (uint32_t)nrhs;
+        const int p = parity >= 0 ? parity : (int)blk;
         int x[4];
-        lex_coords(g, s, x);
-        const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
-        if (parity >= 0 && p != parity) continue;
-        const int blk = parity >= 0 ? 0 : p;
+        site_coords(g, i, p, x);
+        const uint32_t s = (uint32_t)x[0] +
+                           (uint32_t)g.L[0] * ((uint32_t)x[1] + (uint32_t)g.L[1] *
+                                               ((uint32_t)x[2] + (uint32_t)g.L[2] * (uint32_t)x[3]));
         const SpinorBlock<F> in((const char *)src + blk * block_bytes, g.S, nrhs);
         cpx<R> v[12];
-        in.load(s >> 1, r, v);
-        cpx<double> *o = dst + (size_t)t * 12;
+        in.load(i, r, v);
+        cpx<double> *o = dst + ((size_t)r * V + s) * 12;
 #pragma unroll
         for (int c = 0; c < 12; ++c) o[c] = {(double)v[c].x, (double)v[c].y};
     }
