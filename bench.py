@@ -115,7 +115,7 @@ def hop_mode(args):
             pin = lat.pack(psi, prec, 1)
             del psi
             out = lat.empty_packed(prec, nrhs, 0)
-            for _ in range(3):
+            for _ in range(max(3, args.iters)):  # warm caches and clocks as long as we time
                 lat.dslash(out, pin, cola.COLA_OP_HOP, 0, prec, nrhs)
             torch.cuda.synchronize()
             lat.reset_stats()

@@ -158,15 +158,21 @@ TuneEntry default_entry(const Geom &g, int prec, int nrhs) {
     t.sites_per_block = T;
     t.grid = 0;
     t.tchunk = default_tchunk(g, G);
-    // Spatial tiles for the multi-rhs FP16 / FP32 hops, where they measured fastest on a
-    // 32^3 x 64 lattice: (y, z) tiles of 8x8 (FP16; fastest in three of four runs on
-    // different boxes, and the fewest L2 read misses) and 16x8 (FP32) columns walked
-    // through t; 4x8 for multi-rhs FP64 (the outer residuals of the mixed solvers).
-    // Lattices the tile does not divide, and single-rhs hops, keep the time-chunk order.
+    // Spatial tiles ((y, z) columns walked through t) where they measured fastest on a
+    // 32^3 x 64 lattice: for multi-rhs hops 8x8 (FP16; fastest in three of four runs on
+    // different boxes, and the fewest L2 read misses), 16x8 (FP32) and 4x8 (FP64, the
+    // outer residuals of the mixed solvers).  Lattices a tile does not divide keep the
+    // time-chunk order.
     int ty = 0, tz = 0;
+    const bool f64 = prec == COLA_FP64 || prec == COLA_FP64_12;
     if (nrhs >= 4 && prec == COLA_FP16) ty = 8, tz = 8;
     if (nrhs >= 4 && prec == COLA_FP32) ty = 16, tz = 8;
-    if (nrhs >= 4 && (prec == COLA_FP64 || prec == COLA_FP64_12)) ty = 4, tz = 8;  // tuner's pick
+    if (nrhs >= 4 && f64) ty = 4, tz = 8;  // the tuner's pick
+    // single-rhs hops: the tuner's picks on 32^3 x 64 (16x16 tiles of 64-site blocks for
+    // FP64, 16x8 tiles for FP16, plain order in 128-site blocks for FP32)
+    if (nrhs == 1 && f64) ty = 16, tz = 16, t.sites_per_block = 64;
+    if (nrhs == 1 && prec == COLA_FP16) ty = 16, tz = 8;
+    if (nrhs == 1 && prec == COLA_FP32) t.tchunk = 1, t.sites_per_block = 128;
     if (ty > 0 && tile_ok(g, ty, tz)) {
         t.tile_y = ty;
         t.tile_z = tz;
