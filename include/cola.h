@@ -109,7 +109,9 @@ typedef struct {
     int system;            /* COLA_SYS_*                                                */
     int scheme;            /* COLA_CG_*                                                 */
     int block;             /* 0: independent CG per column, batched (lockstep);
-                              1: block CG sharing one Krylov space (FP64 and defect inner) */
+                              1: O'Leary block CG sharing one Krylov space, as the inner
+                              solver of the DEFECT schemes on the SCHUR and PROPAGATOR
+                              systems (COLA_EINVAL otherwise)                          */
     double tol;            /* stop when ||b - A x|| / ||b|| <= tol for every column,
                               A the system's operator, checked in FP64                   */
     int max_iter;          /* cap on (inner) iterations, summed over outer cycles       */
