@@ -54,7 +54,13 @@ enum Epilogue : int {
     EPI_XPAY = 1,        // out = x + a D in
     EPI_CLOV = 2,        // out = C (D in)              C: clover blocks of the output parity
     EPI_CLOV_XPAY = 3,   // out = C x + a D in
-    EPI_XPAY_CLOV = 4    // out = C (x + a D in)
+    EPI_XPAY_CLOV = 4,   // out = C (x + a D in)
+    // CG step fused into the last hop of the normal operator: with o = x + a D in
+    // (EPI_XPAY_CG) or C x + a D in (EPI_CLOV_XPAY_CG), and per rhs
+    // alpha = active ? rho / (pi + pi2) : 0:  cg_x += alpha cg_p,  cg_r -= alpha o;
+    // o itself is not stored and the fused norm is |cg_r|^2
+    EPI_XPAY_CG = 5,
+    EPI_CLOV_XPAY_CG = 6
 };
 
 struct Cplx64 {
@@ -92,6 +98,12 @@ struct HopArgs {
     // host only: when set, the launcher stores the kernel's resident blocks per CU here
     // instead of launching
     int *occupancy;
+    // CG epilogues: the solver's vectors (parity `parity` blocks of the launch format)
+    // and its per-rhs scalars
+    void *cg_x, *cg_r;
+    const void *cg_p;
+    const double *cg_rho, *cg_pi, *cg_pi2;
+    const int *cg_active;
 };
 
 // Deterministic reductions.  Kernels write per-block partial sums, column-major

@@ -117,8 +117,21 @@ struct HopCall {
     double a = 0;
     const void *clov = nullptr;
     double *norm_result = nullptr;  // per-rhs |out|^2 (fused)
+    // EPI_XPAY_CG / EPI_CLOV_XPAY_CG: the CG vectors and per-rhs scalars
+    void *cg_x = nullptr, *cg_r = nullptr;
+    const void *cg_p = nullptr;
+    const double *cg_rho = nullptr, *cg_pi = nullptr, *cg_pi2 = nullptr;
+    const int *cg_active = nullptr;
 };
 int hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, hipStream_t st);
+
+// One CG step on the even-odd normal system S^dag S, with the update fused into the
+// last hop: pi = |S p|^2, then with alpha = rho / pi per active rhs,
+//   x += alpha p,  r -= alpha S^dag S p,  rho_new = |r|^2.
+// x, r, p: even-parity blocks in the storage of prec.
+int schur_normal_cg_step(cola_handle_t *h, int prec, int nrhs, hipStream_t st, void *x, void *r,
+                         const void *p, const double *rho, double *pi, const int *active,
+                         double *rho_new);
 
 // composite operators on packed fields (see COLA_OP_*); norm_result (optional)
 // receives |out|^2 per rhs where the composition allows it to be fused.

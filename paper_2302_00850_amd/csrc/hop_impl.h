@@ -17,6 +17,8 @@
 //   EPI_CLOV       out = C (D in)
 //   EPI_CLOV_XPAY  out = C x + a D in
 //   EPI_XPAY_CLOV  out = C (x + a D in)
+//   EPI_XPAY_CG, EPI_CLOV_XPAY_CG: the CG update of x and r with o = x + a D in
+//                  (or C x + a D in) in place of storing o
 // and |out|^2 per rhs can be accumulated: per-block partials, summed in block
 // order by a reduce_partials launch that follows.
 #pragma once
@@ -156,6 +158,9 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     const SpinorBlock<SF, true> in(a.in, g.S, a.nrhs);
     const SpinorBlock<SF, true> out(a.out, g.S, a.nrhs);
     const SpinorBlock<SF, true> xin(a.x ? a.x : a.out, g.S, a.nrhs);
+    const SpinorBlock<SF, true> cgx(a.cg_x ? a.cg_x : a.out, g.S, a.nrhs);
+    const SpinorBlock<SF, true> cgr(a.cg_r ? a.cg_r : a.out, g.S, a.nrhs);
+    const SpinorBlock<SF, true> cgp(a.cg_p ? a.cg_p : a.out, g.S, a.nrhs);
     const T sg_f = a.dagger ? (T)1 : (T)-1;
     double nrm[RPT];
 #pragma unroll
@@ -242,11 +247,12 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
         hop_dir<3, 1, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fb);
 
         const T ca = (T)a.a;
+        constexpr bool CG = EPI == EPI_XPAY_CG || EPI == EPI_CLOV_XPAY_CG;
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const uint32_t rr = j * RPT + r;
             C *o = acc[r];  // the epilogue result replaces the accumulator
-            if constexpr (EPI == EPI_XPAY) {
+            if constexpr (EPI == EPI_XPAY || EPI == EPI_XPAY_CG) {
                 C xv[12];
                 xin.load(i, rr, xv);
 #pragma unroll
@@ -256,7 +262,7 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) d[c] = o[c];
                 clover_apply<CR, T>(a.clov, g.S, p, i, d, o);
-            } else if constexpr (EPI == EPI_CLOV_XPAY) {
+            } else if constexpr (EPI == EPI_CLOV_XPAY || EPI == EPI_CLOV_XPAY_CG) {
                 C xv[12], cx[12];
                 xin.load(i, rr, xv);
                 clover_apply<CR, T>(a.clov, g.S, p, i, xv, cx);
@@ -269,11 +275,34 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
                 for (int c = 0; c < 12; ++c) xv[c] = add_s(xv[c], ca, o[c]);
                 clover_apply<CR, T>(a.clov, g.S, p, i, xv, o);
             }
-            if constexpr (SF != SpinorFmt::F16) out.store(i, rr, o);
+            if constexpr (CG) {
+                // x += alpha p, r -= alpha o; o becomes the stored r (for the norm)
+                const double den = a.cg_pi[rr] + (a.cg_pi2 ? a.cg_pi2[rr] : 0.0);
+                const T al = (T)(a.cg_active[rr] && den != 0.0 ? a.cg_rho[rr] / den : 0.0);
+                {
+                    C xv[12], pv[12];
+                    cgx.load(i, rr, xv);
+                    cgp.load(i, rr, pv);
+#pragma unroll
+                    for (int c = 0; c < 12; ++c)
+                        xv[c] = {fma(al, pv[c].x, xv[c].x), fma(al, pv[c].y, xv[c].y)};
+                    cgx.store(i, rr, xv);
+                }
+                C rv[12];
+                cgr.load(i, rr, rv);
+#pragma unroll
+                for (int c = 0; c < 12; ++c)
+                    rv[c] = {fma(-al, o[c].x, rv[c].x), fma(-al, o[c].y, rv[c].y)};
+                cgr.store(i, rr, rv);  // rv: now the stored (rounded) values
+#pragma unroll
+                for (int c = 0; c < 12; ++c) o[c] = rv[c];
+            } else if constexpr (SF != SpinorFmt::F16) {
+                out.store(i, rr, o);
+            }
         }
         // FP16: one wide store per component for the lane's RPT right-hand sides;
         // acc then holds the stored (rounded) values
-        if constexpr (SF == SpinorFmt::F16)
+        if constexpr (SF == SpinorFmt::F16 && !CG)
             out.template store_group<RPT>(i, j * RPT, acc, a.want_norm != 0);
         if (a.want_norm) {
 #pragma unroll
@@ -314,6 +343,10 @@ hipError_t hop_launch_epi(const HopArgs &a, int grid, int block, hipStream_t st)
             return hop_launch_t<SF, LF, CR, RPT, EPI_CLOV_XPAY, RPH, SHL>(a, grid, block, st);
         case EPI_XPAY_CLOV:
             return hop_launch_t<SF, LF, CR, RPT, EPI_XPAY_CLOV, RPH, SHL>(a, grid, block, st);
+        case EPI_XPAY_CG:
+            return hop_launch_t<SF, LF, CR, RPT, EPI_XPAY_CG, RPH, SHL>(a, grid, block, st);
+        case EPI_CLOV_XPAY_CG:
+            return hop_launch_t<SF, LF, CR, RPT, EPI_CLOV_XPAY_CG, RPH, SHL>(a, grid, block, st);
     }
     return hipErrorInvalidValue;
 }

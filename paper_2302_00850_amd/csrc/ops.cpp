@@ -88,11 +88,18 @@ void hop_work(const cola_handle_t *h, int prec, int nrhs, int epi, double *bytes
     const double Vh = h->g.Vh;
     double b = 8.0 * link_bytes(lf) + 2.0 * nrhs * spinor_site_bytes(sf);
     double f = 1320.0 * nrhs + (lf == LinkFmt::F64_18 ? 0.0 : 8 * 42.0);
-    if (epi == EPI_XPAY || epi == EPI_CLOV_XPAY || epi == EPI_XPAY_CLOV) {
+    const bool cg = epi == EPI_XPAY_CG || epi == EPI_CLOV_XPAY_CG;
+    if (epi == EPI_XPAY || epi == EPI_CLOV_XPAY || epi == EPI_XPAY_CLOV || cg) {
         b += nrhs * spinor_site_bytes(sf);
         f += 48.0 * nrhs;
     }
-    if (epi == EPI_CLOV || epi == EPI_CLOV_XPAY || epi == EPI_XPAY_CLOV) {
+    if (cg) {
+        // reads x, p, r and writes x, r in place of writing the result
+        b += 4.0 * nrhs * spinor_site_bytes(sf);
+        f += 96.0 * nrhs;
+    }
+    if (epi == EPI_CLOV || epi == EPI_CLOV_XPAY || epi == EPI_XPAY_CLOV ||
+        epi == EPI_CLOV_XPAY_CG) {
         b += 72.0 * (sf == SpinorFmt::F64 ? 8 : 4);
         f += 552.0 * nrhs;
     }
@@ -221,6 +228,13 @@ int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, cons
     a.in = c.in;
     a.out = c.out;
     a.x = c.x;
+    a.cg_x = c.cg_x;
+    a.cg_r = c.cg_r;
+    a.cg_p = c.cg_p;
+    a.cg_rho = c.cg_rho;
+    a.cg_pi = c.cg_pi;
+    a.cg_pi2 = c.cg_pi2;
+    a.cg_active = c.cg_active;
     a.gauge = h->gauge[(int)link_fmt(prec)];
     a.clov = c.clov;
     a.partial = h->partial;
@@ -370,12 +384,18 @@ int hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, hipStream_t st) 
                          "compressed link formats need an SU(3) gauge field (check failed)");
     if (!h->gauge[(int)link_fmt(prec)])
         return set_error(h, COLA_EINVAL, "packed gauge field missing for this precision");
-    const std::string key = tune_key(h, prec, nrhs, c.epi, c.norm_result != nullptr);
+    // The CG epilogues update their vectors in place, so they are never timed by the
+    // tuner: they take the shape tuned for the epilogue they extend, else the default.
+    const bool cg = c.epi == EPI_XPAY_CG || c.epi == EPI_CLOV_XPAY_CG;
+    const int key_epi = c.epi == EPI_XPAY_CG ? EPI_XPAY
+                        : c.epi == EPI_CLOV_XPAY_CG ? EPI_CLOV_XPAY
+                                                    : c.epi;
+    const std::string key = tune_key(h, prec, nrhs, key_epi, c.norm_result != nullptr);
     TuneEntry te;
     auto it = h->tune.find(key);
-    if (it != h->tune.end() && h->tune_mode != 2) {
+    if (it != h->tune.end() && (h->tune_mode != 2 || cg)) {
         te = it->second;
-    } else if (h->tune_mode >= 1) {
+    } else if (h->tune_mode >= 1 && !cg) {
         COLA_TRY(tune_hop(h, c, prec, nrhs, &te, st));
         h->tune[key] = te;
     } else {
@@ -476,6 +496,42 @@ int apply_op(cola_handle_t *h, void *out, const void *in, int op, int parity, in
         }
         default: return set_error(h, COLA_EINVAL, "unknown operator");
     }
+}
+
+int schur_normal_cg_step(cola_handle_t *h, int prec, int nrhs, hipStream_t st, void *x, void *r,
+                         const void *p, const double *rho, double *pi, const int *active,
+                         double *rho_new) {
+    const SpinorFmt sf = spinor_fmt(prec);
+    const size_t bb = spinor_block_bytes(h->g, sf, nrhs);
+    const bool clover = h->csw != 0.0;
+    const bool f64 = sf == SpinorFmt::F64;
+    void *te, *to;
+    // the same work vectors as COLA_OP_SCHUR_DAGSCHUR and COLA_OP_SCHUR
+    COLA_TRY(get_vec(h, "op_even_" + std::to_string((int)sf) + "_" + std::to_string(nrhs), bb,
+                     &te));
+    COLA_TRY(get_vec(h, "op_odd_" + std::to_string((int)sf) + "_" + std::to_string(nrhs), bb,
+                     &to));
+    COLA_TRY(apply_op(h, te, p, COLA_OP_SCHUR, 0, prec, nrhs, st, pi));
+    // S^dag te: t_o = A_oo^-1 D_oe^dag te, then the CG update with A_ee te - kappa^2 D_eo^dag t_o
+    HopCall c1{to, te, 1, 1};
+    if (clover) {
+        c1.epi = EPI_CLOV;
+        c1.clov = f64 ? h->clovinv64 : h->clovinv32;
+    }
+    COLA_TRY(hop(h, c1, prec, nrhs, st));
+    HopCall c2{r, to, 0, 1};
+    c2.epi = clover ? EPI_CLOV_XPAY_CG : EPI_XPAY_CG;
+    c2.x = te;
+    c2.a = -h->kappa * h->kappa;
+    c2.clov = f64 ? h->clov64 : h->clov32;
+    c2.norm_result = rho_new;
+    c2.cg_x = x;
+    c2.cg_r = r;
+    c2.cg_p = p;
+    c2.cg_rho = rho;
+    c2.cg_pi = pi;
+    c2.cg_active = active;
+    return hop(h, c2, prec, nrhs, st);
 }
 
 }  // namespace cola

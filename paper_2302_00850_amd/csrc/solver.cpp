@@ -76,6 +76,25 @@ int normal(const Ctx &c, int prec, void *out, const void *in) {
     return apply_op(h, out, t, COLA_OP_MDAG, -1, prec, c.R, c.st);
 }
 
+// One CG step: Ap = A p, pi = <p, Ap>, then x += alpha p, r -= alpha Ap and
+// rho_new = |r|^2.  On the even-odd system with x, r and p in the operator's storage the
+// update runs inside the last hop (Ap is never stored); COLA_CG_FUSE=0 selects the
+// separate update kernel.
+int cg_step(const Ctx &c, int prec, SpinorFmt fx, void *x, void *r, void *pv, void *ap) {
+    cola_handle_t *h = c.h;
+    const SpinorFmt fp = spinor_fmt(prec);
+    const char *env = getenv("COLA_CG_FUSE");
+    const bool fuse = !c.full && fx == fp && !(env && env[0] == '0');
+    if (fuse)
+        return schur_normal_cg_step(h, prec, c.R, c.st, x, r, pv, c.slot(RHO), c.slot(PI),
+                                    h->active, c.slot(RHO_NEW));
+    COLA_TRY(normal(c, prec, ap, pv));
+    COLA_HIP(h, launch_cg_xr(c.shape(), fx, fp, fx, fp, x, pv, r, ap, c.slot(RHO), c.slot(PI),
+                             c.full ? c.slot(PI2) : nullptr, h->active,
+                             reduce_into(h, RHO_NEW), c.st));
+    return COLA_OK;
+}
+
 int zero_pi2(const Ctx &c) {
     COLA_HIP(c.h, hipMemsetAsync(c.slot(PI2), 0, sizeof(double) * kMaxRhs, c.st));
     return COLA_OK;
@@ -201,9 +220,7 @@ int solve_reliable(const Ctx &c, int sloppy_prec, const cola_cg_params_t &p, voi
     int last_rel = 0;
     int it = 0;
     while (it < p.max_iter) {
-        COLA_TRY(normal(c, sloppy_prec, aps, ps));
-        COLA_HIP(h, launch_cg_xr(sh, fs, fs, fs, fs, xs, ps, rs, aps, c.slot(RHO), c.slot(PI),
-                                 c.full ? c.slot(PI2) : nullptr, h->active, red_new, c.st));
+        COLA_TRY(cg_step(c, sloppy_prec, fs, xs, rs, ps, aps));
         ++it;
         bool stop = false;
         if (it % check == 0 || it == p.max_iter) {
@@ -288,14 +305,11 @@ int inner_cg(const Ctx &c, int prec, SpinorFmt fx, void *x, void *r, void *pv, v
     cola_handle_t *h = c.h;
     const BlasShape sh = c.shape();
     const SpinorFmt fp = spinor_fmt(prec);
-    const Reduce red_new = reduce_into(h, RHO_NEW);
     COLA_TRY(write_active(c, act));
     std::vector<double> rho(c.R);
     int it = 0;
     while (it < max_it) {
-        COLA_TRY(normal(c, prec, ap, pv));
-        COLA_HIP(h, launch_cg_xr(sh, fx, fp, fx, fp, x, pv, r, ap, c.slot(RHO), c.slot(PI),
-                                 c.full ? c.slot(PI2) : nullptr, h->active, red_new, c.st));
+        COLA_TRY(cg_step(c, prec, fx, x, r, pv, ap));
         ++it;
         if (it % check == 0) {
             COLA_TRY(read_slot(c, RHO_NEW, rho.data()));

@@ -57,8 +57,11 @@ def _normal_residual(U, x, b, system, kappa, bc, A=None, Ai=None):
     return rel(ax, be)
 
 
-@pytest.mark.parametrize("system", [cola.COLA_SYS_MDAGM, cola.COLA_SYS_SCHUR])
-def test_cg_fp64_fixed_iterations_match_oracle(fields, system):
+@pytest.mark.parametrize("system,fuse", [(cola.COLA_SYS_MDAGM, "1"), (cola.COLA_SYS_SCHUR, "1"),
+                                         (cola.COLA_SYS_SCHUR, "0")])
+def test_cg_fp64_fixed_iterations_match_oracle(fields, system, fuse, monkeypatch):
+    """fuse: the even-odd CG update inside the last hop (1) or as its own kernel (0)."""
+    monkeypatch.setenv("COLA_CG_FUSE", fuse)
     U, b = fields
     sysid = 0 if system == cola.COLA_SYS_MDAGM else 1
     _, n, _ = oracle.cg(U, b[0], KAPPA, GENERIC, system=sysid, tol=1e-10)
@@ -151,6 +154,33 @@ def test_cg_clover_schur(fields, scheme):
     xs = x.cpu().numpy()
     for q in range(2):
         assert _normal_residual(U, xs[q], b[q], cola.COLA_SYS_SCHUR, kappa, ANTI, A, Ai) <= 1.05e-10
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("csw", [0.0, 1.0])
+def test_cg_fused_update_matches_separate(fields, scheme, csw, monkeypatch):
+    """The CG update fused into the last hop of S^dag S against the separate update
+    kernel: both reach the tolerance, in about as many iterations, at the same
+    solutions (to the tolerance times the condition number)."""
+    U, b = fields
+    kappa = 0.118 if csw else KAPPA
+    A = oracle.clover(U, kappa, csw) if csw else None
+    Ai = oracle.site_inverse(A) if csw else None
+    src = point_sources(DIMS).numpy()
+    lat = _lat(U, ANTI, csw=csw, kappa=kappa)
+    out = {}
+    for fuse in ("0", "1"):
+        monkeypatch.setenv("COLA_CG_FUSE", fuse)
+        x, info = lat.cg(_cuda(src), system=cola.COLA_SYS_SCHUR, scheme=scheme, tol=1e-10)
+        assert info["status"] == cola.COLA_OK, (fuse, info)
+        out[fuse] = (x.cpu().numpy(), info)
+    xs = out["1"][0]
+    for q in range(12):
+        r = _normal_residual(U, xs[q], src[q], cola.COLA_SYS_SCHUR, kappa, ANTI, A, Ai)
+        assert r <= 1.05e-10, (q, r)
+    n0, n1 = out["0"][1]["iterations"], out["1"][1]["iterations"]
+    assert abs(n1 - n0) <= max(2, n0 // 10), (n0, n1)
+    assert rel(xs, out["0"][0]) < 1e-7
 
 
 @pytest.mark.parametrize("csw", [0.0, 1.0])
