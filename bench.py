@@ -7,7 +7,9 @@ spin-colour point sources at the origin.  One step = one solve of
 S^H S x_e = b_e for all 12 sources to a 1e-10 FP64 true relative residual,
 with FP16-storage CG (FP32 arithmetic, 12-RHS batched hop) inside FP64 defect
 correction.  Reported value: effective GB/s of the FP16 12-RHS hop kernel
-(algorithmic bytes / HIP-event kernel time over the timed steps); also the
+(algorithmic bytes / HIP-event kernel time over the timed steps, over its four
+launches per CG iteration: two plain hops, one with the x - kappa^2 D in epilogue
+and |out|^2, one with the CG update of x and r fused in); also the
 time per source against plain FP64 CG (one source, 18-real links) and the
 FP64 CPU oracle on the machine's host cores.
 
