@@ -194,6 +194,7 @@ TuneEntry default_entry(const Geom &g, int prec, int nrhs) {
         const int n = sscanf(env, "%d,%d,%d,%d,%d,%d,%d", &e.rpt, &e.sites_per_block, &e.grid,
                              &e.tchunk, &e.tile_y, &e.tile_z, &e.stage);
         if ((n == 4 || n == 6 || n == 7) && (e.rpt >= 1 && e.rpt <= 4) && nrhs % e.rpt == 0 &&
+            (e.rpt == 1 || !f64) &&
             e.sites_per_block >= 1 && (e.sites_per_block & (e.sites_per_block - 1)) == 0 &&
             e.sites_per_block * (nrhs / e.rpt) <= 256 && e.grid >= -1 && e.tchunk >= 1 &&
             g.L[3] % e.tchunk == 0 && tile_ok(g, e.tile_y, e.tile_z) &&

@@ -4,7 +4,8 @@ benchmark uses:
 * hop / M (with clover) outputs on sampled sites against the oracle's per-site
   evaluation (32^3x64 FP16 x 12 rhs and FP32, 48^3x96 clover FP32 and FP64);
 * the free-field propagator at 32^3x64 against its closed form in momentum
-  space (FFT), for the FP64 and FP16-defect solvers;
+  space (FFT), for the FP64 and FP16-defect solvers, on the full lattice and
+  through the even-odd system with the fused CG update;
 * the fermion force at 24^3x48 against a local-resolvent central finite
   difference on 64 links and against the oracle's force on every link.
 """
@@ -124,6 +125,27 @@ def test_free_field_propagator_32x64():
     p = pts.cpu().numpy()
     for q in range(2):
         assert rel(xs[q], _free_prop(p[q], dims, kappa)) < 3e-7
+
+
+def test_free_field_propagator_schur_fused_32x64():
+    """The benchmark's path at its shape: even-odd (Schur) FP16 defect correction with
+    the CG update fused into the last hop, solving M x = b for 2 point sources with
+    U = 1.  Closed form: x = M^H (M^H M)^-1 b, the momentum-space inverse above with
+    M^H applied by the oracle."""
+    dims = (32, 32, 32, 64)
+    kappa = 0.12
+    lat = cola.Lattice(dims, kappa, ANTI)
+    lat.set_gauge(unit_gauge(dims, device="cuda"))
+    pts = point_sources(dims, device="cuda")[[3, 10]].contiguous()
+    x, info = lat.cg(pts, system=cola.COLA_SYS_PROPAGATOR, scheme=cola.COLA_CG_FP16_DEFECT,
+                     tol=1e-10)
+    assert info["status"] == cola.COLA_OK, info
+    xs = x.cpu().numpy()
+    p = pts.cpu().numpy()
+    U1 = unit_gauge(dims).numpy()
+    for q in range(2):
+        ref = oracle.apply_M(U1, _free_prop(p[q], dims, kappa), kappa, ANTI, dagger=True)
+        assert rel(xs[q], ref) < 3e-7
 
 
 def _link_sites(site, mu, dims):

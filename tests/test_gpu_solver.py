@@ -183,6 +183,27 @@ def test_cg_fused_update_matches_separate(fields, scheme, csw, monkeypatch):
     assert rel(xs, out["0"][0]) < 1e-7
 
 
+@pytest.mark.parametrize("scheme", [cola.COLA_CG_FP16_DEFECT, cola.COLA_CG_FP32_DEFECT])
+@pytest.mark.parametrize("shape", ["2,16,0,1", "1,16,-1,2", "1,16,0,1,2,2,1", "2,16,5,1,2,2,1",
+                                   "3,16,0,1,2,2"])
+def test_cg_fused_update_launch_shapes(fields, scheme, shape, monkeypatch):
+    """The fused CG update under launch shapes other than the default (several rhs per
+    lane, resident and ragged grids, time chunks, tiles, staged links): the solve reaches
+    the tolerance at the default shape's solutions."""
+    U, b = fields
+    src = point_sources(DIMS).numpy()
+    lat = _lat(U, GENERIC)
+    monkeypatch.delenv("COLA_HOP_SHAPE", raising=False)
+    x0, _ = lat.cg(_cuda(src), system=cola.COLA_SYS_SCHUR, scheme=scheme, tol=1e-10)
+    monkeypatch.setenv("COLA_HOP_SHAPE", shape)
+    x, info = lat.cg(_cuda(src), system=cola.COLA_SYS_SCHUR, scheme=scheme, tol=1e-10)
+    assert info["status"] == cola.COLA_OK, info
+    xs = x.cpu().numpy()
+    for q in (0, 5, 11):
+        assert _normal_residual(U, xs[q], src[q], cola.COLA_SYS_SCHUR, KAPPA, GENERIC) <= 1.05e-10
+    assert rel(xs, x0.cpu().numpy()) < 1e-7
+
+
 @pytest.mark.parametrize("csw", [0.0, 1.0])
 def test_propagator_solves_M(fields, csw):
     U, b = fields
