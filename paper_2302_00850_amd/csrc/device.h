@@ -188,24 +188,32 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_u(const void *base, uint32
                                              0x00020000);
 }
 
-template <typename E>
+// Cache policy of a buffer access (the instruction's cache-policy immediate): 0 is the
+// default, kCpolNT sets the nontemporal bit.  Every field store is nontemporal: outputs
+// are written once per launch and read by a later launch, and the hint keeps them from
+// displacing the neighbour spinors that the hop reuses from L2.  Loads of data used
+// once per launch (a site's own spinors in epilogues and vector kernels, clover blocks,
+// and the links of one-lane-per-site hops) are nontemporal for the same reason.
+constexpr int kCpolNT = 2;
+
+template <typename E, int CP = 0>
 __device__ __forceinline__ E bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     E v;
     if constexpr (sizeof(E) == 2) {
-        const unsigned short w = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+        const unsigned short w = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, CP);
         __builtin_memcpy(&v, &w, 2);
     } else if constexpr (sizeof(E) == 4) {
-        const unsigned int w = __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+        const unsigned int w = __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, CP);
         __builtin_memcpy(&v, &w, 4);
     } else if constexpr (sizeof(E) == 8) {
-        const u32x2_t w = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+        const u32x2_t w = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, CP);
         __builtin_memcpy(&v, &w, 8);
     } else if constexpr (sizeof(E) == 12) {
-        const u32x3_t w = __builtin_amdgcn_raw_buffer_load_b96(r, (int)off, 0, 0);
+        const u32x3_t w = __builtin_amdgcn_raw_buffer_load_b96(r, (int)off, 0, CP);
         __builtin_memcpy(&v, &w, 12);
     } else {
         static_assert(sizeof(E) == 16, "16-byte element");
-        const u32x4_t w = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+        const u32x4_t w = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, CP);
         __builtin_memcpy(&v, &w, 16);
     }
     return v;
@@ -216,20 +224,20 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, c
     if constexpr (sizeof(E) == 4) {
         unsigned int w;
         __builtin_memcpy(&w, &v, 4);
-        __builtin_amdgcn_raw_buffer_store_b32(w, r, (int)off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(w, r, (int)off, 0, kCpolNT);
     } else if constexpr (sizeof(E) == 8) {
         u32x2_t w;
         __builtin_memcpy(&w, &v, 8);
-        __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)off, 0, kCpolNT);
     } else if constexpr (sizeof(E) == 12) {
         u32x3_t w;
         __builtin_memcpy(&w, &v, 12);
-        __builtin_amdgcn_raw_buffer_store_b96(w, r, (int)off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b96(w, r, (int)off, 0, kCpolNT);
     } else {
         static_assert(sizeof(E) == 16, "16-byte element");
         u32x4_t w;
         __builtin_memcpy(&w, &v, 16);
-        __builtin_amdgcn_raw_buffer_store_b128(w, r, (int)off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(w, r, (int)off, 0, kCpolNT);
     }
 }
 
@@ -261,7 +269,7 @@ struct SpinorBlock {
     // the 12 components of site i, rhs r, in compute precision
     __device__ __forceinline__ void load(uint32_t i, uint32_t r, cpx<R> v[12]) const {
         R s;
-        load_unscaled(i, r, v, &s);
+        load_unscaled<kCpolNT>(i, r, v, &s);
         if constexpr (F == SpinorFmt::F16) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) v[c] = {s * v[c].x, s * v[c].y};
@@ -269,18 +277,19 @@ struct SpinorBlock {
     }
 
     // The 12 components without the FP16 site scale; *scale receives it (1 otherwise).
+    template <int CP = 0>
     __device__ __forceinline__ void load_unscaled(uint32_t i, uint32_t r, cpx<R> v[12],
                                                   R *scale) const {
         const uint32_t e = i * nrhs + r;
         const uint32_t off = e * (uint32_t)sizeof(E);
         if constexpr (F == SpinorFmt::F16) {
-            *scale = bload<float>(nrm(), e * 4u);
+            *scale = bload<float, CP>(nrm(), e * 4u);
         } else {
             *scale = (R)1;
         }
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            const E h = bload<E>(comp(c), off);
+            const E h = bload<E, CP>(comp(c), off);
             v[c] = {(R)h.x, (R)h.y};
         }
     }
@@ -419,8 +428,8 @@ __device__ __forceinline__ void rebuild_row2(cpx<T> u[3][3]) {
 
 // Load U_mu at checkerboard site i of parity p; row 2 rebuilt as conj(row0 x row1)
 // for the 12-real formats.
-// UNI: parity p is the same for every lane of the wavefront.
-template <LinkFmt F, typename T, bool UNI = true>
+// UNI: parity p is the same for every lane of the wavefront.  CP: cache policy.
+template <LinkFmt F, typename T, bool UNI = true, int CP = 0>
 __device__ __forceinline__ void load_link(const void *gauge, int S, int p, int mu, uint32_t i,
                                           cpx<T> u[3][3]) {
     using CH = typename LinkT<F>::chunk;
@@ -434,20 +443,20 @@ __device__ __forceinline__ void load_link(const void *gauge, int S, int p, int m
     if constexpr (F == LinkFmt::F64_18) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const CH c = bload<CH>(buf_u(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
+            const CH c = bload<CH, CP>(buf_u(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
             u[k / 3][k % 3] = {(T)c.a, (T)c.b};
         }
         return;
     } else if constexpr (F == LinkFmt::F64_12) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const CH c = bload<CH>(buf_u(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
+            const CH c = bload<CH, CP>(buf_u(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
             u[k / 3][k % 3] = {(T)c.a, (T)c.b};
         }
     } else {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const CH c = bload<CH>(buf_u(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
+            const CH c = bload<CH, CP>(buf_u(base + (size_t)k * S, (uint32_t)S * sizeof(CH)), off);
             u[(2 * k) / 3][(2 * k) % 3] = {(T)c.a, (T)c.b};
             u[(2 * k + 1) / 3][(2 * k + 1) % 3] = {(T)c.c, (T)c.d};
         }
@@ -779,13 +788,15 @@ __device__ __forceinline__ void clover_apply(const void *clov, int S, int p, uin
         cpx<T> o[15];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const pair v = bload<pair>(buf_u(q + (size_t)k * S, (uint32_t)S * sizeof(pair)), off);
+            const pair v =
+                bload<pair, kCpolNT>(buf_u(q + (size_t)k * S, (uint32_t)S * sizeof(pair)), off);
             d[2 * k] = (T)v.a;
             d[2 * k + 1] = (T)v.b;
         }
 #pragma unroll
         for (int k = 0; k < 15; ++k) {
-            const pair v = bload<pair>(buf_u(q + (size_t)(3 + k) * S, (uint32_t)S * sizeof(pair)), off);
+            const pair v =
+                bload<pair, kCpolNT>(buf_u(q + (size_t)(3 + k) * S, (uint32_t)S * sizeof(pair)), off);
             o[k] = {(T)v.a, (T)v.b};
         }
         const cpx<T> *v = in + 6 * blk;

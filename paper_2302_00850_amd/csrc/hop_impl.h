@@ -117,6 +117,9 @@ __device__ __forceinline__ void hop_dir(const HopArgs &a, int p, uint32_t i, con
         C u[3][3];
         if constexpr (SHL && LF == LinkFmt::F32_12)
             read_staged(staged + (2 * MU + DIR) * kStageWords, u);
+        else if (a.groups == 1)  // one lane per site: each link is read by one lane only
+            load_link<LF, T, true, kCpolNT>(a.gauge, g.S, dir == 0 ? p : 1 - p, mu,
+                                            dir == 0 ? i : n, u);
         else
             load_link<LF, T>(a.gauge, g.S, dir == 0 ? p : 1 - p, mu, dir == 0 ? i : n, u);
 #pragma unroll
