@@ -165,16 +165,24 @@ TuneEntry default_entry(const Geom &g, int prec, int nrhs) {
     t.sites_per_block = T;
     t.grid = 0;
     t.tchunk = default_tchunk(g, G);
-    // Spatial tiles ((y, z) columns walked through t) where they measured fastest on a
-    // 32^3 x 64 lattice: for multi-rhs hops 8x8 (FP16; fastest in three of four runs on
-    // different boxes, and the fewest L2 read misses), 16x8 (FP32) and 4x8 (FP64, the
-    // outer residuals of the mixed solvers).  Lattices a tile does not divide keep the
-    // time-chunk order.
+    // Spatial tiles ((y, z) columns walked through t).  Multi-rhs hops: the largest of
+    // 8x8, 8x4 and 4x4 whose timeslice holds at most 1024 sites (Lx/2 ty tz), so that a
+    // few timeslices of a tile stay in one XCD's L2 while it walks t.  Measured: 8x8 on
+    // 32^3 x 64 gave the fastest 12-rhs FP16 solve (8x4 and 4x8 0.4-1.6% slower, 4x4 4%);
+    // on 48^3 x 96, 8x4 and 4x4 ran the 12-rhs FP32 clover solve 9-10% faster than 16x8.
+    // Lattices no candidate divides keep the time-chunk order.
     int ty = 0, tz = 0;
     const bool f64 = prec == COLA_FP64 || prec == COLA_FP64_12;
-    if (nrhs >= 4 && prec == COLA_FP16) ty = 8, tz = 8;
-    if (nrhs >= 4 && prec == COLA_FP32) ty = 16, tz = 8;
-    if (nrhs >= 4 && f64) ty = 4, tz = 8;  // the tuner's pick
+    if (nrhs >= 4) {
+        const int cand[3][2] = {{8, 8}, {8, 4}, {4, 4}};
+        for (const auto &c : cand) {
+            if (g.Lxh * c[0] * c[1] <= 1024 && tile_ok(g, c[0], c[1])) {
+                ty = c[0];
+                tz = c[1];
+                break;
+            }
+        }
+    }
     // single-rhs hops: the tuner's picks on 32^3 x 64 (16x16 tiles of 64-site blocks for
     // FP64, 16x8 tiles for FP16, plain order in 128-site blocks for FP32)
     if (nrhs == 1 && f64) ty = 16, tz = 16, t.sites_per_block = 64;
