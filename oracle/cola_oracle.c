@@ -24,10 +24,12 @@
  * (site*4 + spin)*3 + colour; link entry ((site*4 + mu)*3 + row)*3 + col.
  * Parity of a site = (x+y+z+t) mod 2.
  *
- * Parity unpinned: the overall sign of the clover term (the convention
- * A = 1 - kappa*c_sw*sum_{mu<nu} sigma_mu,nu F_mu,nu is a reading, not fixed
- * by anything the paper prints).  Every other function here is pinned by
- * closed forms, invariants or brute force in the CPU test-suite.
+ * The clover convention A = 1 - kappa*c_sw*sum_{mu<nu} sigma_mu,nu F_mu,nu is a
+ * reading (the paper prints no formula); its overall sign and normalisation are
+ * pinned by tree-level O(a) improvement: in a constant abelian field, c_sw = 1
+ * cancels the Wilson term's shift of the would-be zero modes.  Every function
+ * here is pinned by closed forms, invariants or brute force in the CPU
+ * test-suite.
  */
 #include <complex.h>
 #include <math.h>

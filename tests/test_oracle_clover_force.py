@@ -2,7 +2,8 @@
 
 Clover: A = 1 at U = 1, Hermitian, block-diagonal in chirality, gauge
 covariant, and the closed form of a constant abelian flux.  The overall sign
-of the clover term is a convention the paper does not fix (parity unpinned).
+is fixed by tree-level O(a) improvement: in a constant abelian field the clover
+term at c_sw = 1 cancels the Wilson term's shift of the would-be zero modes.
 
 Force: finite differences of the action S = phi^H (M^H M)^{-1} phi computed
 by dense solves (a route that never touches the oracle's force code), the
@@ -79,6 +80,71 @@ def test_clover_constant_abelian_flux():
     expect = np.eye(12) - kappa * csw * np.sin(phi) * np.kron(sig, np.diag([1, -1, 0]))
     A = oracle.clover(U, kappa, csw)
     np.testing.assert_allclose(A, np.broadcast_to(expect, A.shape), atol=1e-14)
+
+
+def _constant_flux_gauge(dims, mu, nu, flux=1):
+    """U(1) field of constant strength f = 2 pi flux / (L_mu L_nu) in the (mu, nu) plane,
+    embedded as diag(e^{i th}, e^{-i th}, 1): U_nu(x) carries th = f x_mu, and U_mu at
+    x_mu = L_mu - 1 carries th = -f L_mu x_nu (the torus twist), every other link is 1.
+    Every (mu, nu) plaquette is then e^{i f} on colour 0."""
+    L = dims
+    f = 2 * np.pi * flux / (L[mu] * L[nu])
+    U = unit_gauge(dims).numpy()
+    shape = (L[3], L[2], L[1], L[0])
+    xm = np.arange(L[mu]).reshape([-1 if 3 - a == mu else 1 for a in range(4)])
+    xn = np.arange(L[nu]).reshape([-1 if 3 - a == nu else 1 for a in range(4)])
+    th_nu = np.broadcast_to(f * xm, shape)
+    th_mu = np.broadcast_to(np.where(xm == L[mu] - 1, -f * L[mu] * xn, 0.0 * xn), shape)
+    for d, th in ((nu, th_nu), (mu, th_mu)):
+        U[..., d, 0, 0] = np.exp(1j * th)
+        U[..., d, 1, 1] = np.exp(-1j * th)
+    return U, f
+
+
+@pytest.mark.parametrize("mu,nu", [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)])
+def test_clover_cancels_the_wilson_pauli_term(mu, nu):
+    """Tree-level O(a) improvement fixes the clover term's overall sign.  In a constant
+    abelian field f the massless continuum operator has exact zero modes (index
+    theorem; two per unit flux here, for colour 0 constant in the short directions).
+    The Wilson term turns them into real eigenvalues f/2 of the massless lattice
+    operator 4 - D/2 (its O(a) Pauli term); the clover term at c_sw = 1 exists to
+    cancel exactly that, leaving O(f^2); with the opposite sign they move to f."""
+    dims = [2, 2, 2, 2]
+    dims[mu] = dims[nu] = 8
+    dims = tuple(dims)
+    U, f = _constant_flux_gauge(dims, mu, nu)
+    # the field is what it should be: F_mu_nu = sin(f) diag(1, -1, 0) at every site
+    F = oracle.field_strength(U, mu, nu)
+    np.testing.assert_allclose(F, np.broadcast_to(np.sin(f) * np.diag([1, -1, 0]), F.shape),
+                               atol=1e-13)
+    kappa = 0.125
+    A = oracle.clover(U, kappa, 1.0)
+    V = int(np.prod(dims))
+    shape = (dims[3], dims[2], dims[1], dims[0])
+    K = np.zeros((4 * V, 4 * V), complex)  # 4 - D/2 on colour 0
+    S = np.zeros((4 * V, 4 * V), complex)  # (A - 1) / (2 kappa) on colour 0
+    per = bc_phases((0, 0, 0, 0))
+    for site in range(V):
+        at = np.unravel_index(site, shape)
+        for sp in range(4):
+            psi = np.zeros(shape + (4, 3), complex)
+            psi[at + (sp, 0)] = 1
+            K[:, 4 * site + sp] = (4 * psi - 0.5 * oracle.hop(U, psi, per))[..., 0].ravel()
+            Ap = np.einsum("...ab,...b->...a", A, psi.reshape(shape + (12,))).reshape(psi.shape)
+            S[:, 4 * site + sp] = ((Ap - psi) / (2 * kappa))[..., 0].ravel()
+
+    def lowest(c):
+        ev = np.linalg.eigvals(K + c * S)
+        return ev[np.argsort(np.abs(ev))[:3]]
+
+    wil, imp, flip = lowest(0.0), lowest(1.0), lowest(-1.0)
+    for ev, target in ((wil, f / 2), (flip, f)):
+        assert np.abs(ev[:2].imag).max() < 1e-10
+        np.testing.assert_allclose(ev[:2].real, target, rtol=0.05)
+    assert np.abs(imp[:2]).max() < 0.03 * f / 2
+    # the would-be zero modes are isolated from the rest of the spectrum
+    for ev in (wil, imp, flip):
+        assert np.abs(ev[2]) > 4 * np.abs(ev[1])
 
 
 # ------------------------------------------------------------------- force
