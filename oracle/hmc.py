@@ -1,0 +1,126 @@
+"""FP64 CPU oracle for one HMC trajectory (plain numpy; TEST INFRASTRUCTURE ONLY).
+
+Hybrid Monte Carlo (the gauge-field generation method the paper lists among its
+algorithms, with the Duane et al. reference) for SU(3) links with the Wilson gauge
+action and, optionally, two flavours of plain Wilson fermions through one
+pseudofermion field:
+
+  H(U, P) = sum_links Tr(P^2) / 2 + S_g(U) + S_f(U)
+  S_g = beta sum_{x, mu<nu} (1 - Re Tr U_mu,nu(x) / 3)       (plaquette action)
+  S_f = phi^H (M^H M)^{-1} phi                               (M = 1 - kappa D)
+
+P is traceless Hermitian per link.  A link moves as U -> exp(i eps P) U and the
+force F(U) is the traceless Hermitian matrix with dS/de = Tr(H F) along
+U -> exp(i e H) U, so that dP/dtau = -F conserves H.  The integrator is leapfrog:
+half step in P, n alternating full steps, half step in P.
+
+Nothing here is shared with the GPU library; the fermion parts call the C oracle
+(CG, M and the fermion force in its Lie-algebra form).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+
+def _dag(a):
+    return np.conj(np.swapaxes(a, -1, -2))
+
+
+def _shift(a, mu, s):
+    """b(x) = a(x + s mu) on the periodic lattice (arrays indexed [t][z][y][x])."""
+    return np.roll(a, -s, axis=3 - mu)
+
+
+def plaquettes(U):
+    """U_mu,nu(x) = U_mu(x) U_nu(x+mu) U_mu(x+nu)^H U_nu(x)^H for mu < nu."""
+    out = {}
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            Um, Un = U[..., mu, :, :], U[..., nu, :, :]
+            out[mu, nu] = Um @ _shift(Un, mu, 1) @ _dag(_shift(Um, nu, 1)) @ _dag(Un)
+    return out
+
+
+def gauge_action(U, beta):
+    """Wilson plaquette action beta sum (1 - Re Tr U_plaq / 3)."""
+    s = 0.0
+    for P in plaquettes(U).values():
+        s += np.sum(1.0 - np.real(np.einsum("...ii->...", P)) / 3.0)
+    return beta * s
+
+
+def staples(U, mu):
+    """A_mu(x) with sum over plaquettes containing U_mu(x) of Re Tr = Re Tr(U_mu(x) A_mu(x)):
+    for each nu != mu the upper staple U_nu(x+mu) U_mu(x+nu)^H U_nu(x)^H and the lower
+    one U_nu(x+mu-nu)^H U_mu(x-nu)^H U_nu(x-nu)."""
+    A = np.zeros(U.shape[:4] + (3, 3), dtype=np.complex128)
+    Um = U[..., mu, :, :]
+    for nu in range(4):
+        if nu == mu:
+            continue
+        Un = U[..., nu, :, :]
+        A += _shift(Un, mu, 1) @ _dag(_shift(Um, nu, 1)) @ _dag(Un)
+        Un_m = _shift(Un, nu, -1)                      # U_nu(x - nu)
+        A += _dag(_shift(Un_m, mu, 1)) @ _dag(_shift(Um, nu, -1)) @ Un_m
+    return A
+
+
+def traceless_hermitian(X):
+    H = 0.5 * (X + _dag(X))
+    tr = np.einsum("...ii->...", H)
+    return H - tr[..., None, None] / 3.0 * np.eye(3)
+
+
+def gauge_force(U, beta):
+    """F_mu(x) for S_g: with W = U_mu(x) A_mu(x), dS_g/de along exp(i e H) U_mu(x) is
+    -(beta/3) Re Tr(i H W) = Tr(H F) for F = -(beta/3) P_TH[i (W - W^H) / 2]."""
+    F = np.empty_like(U)
+    for mu in range(4):
+        W = U[..., mu, :, :] @ staples(U, mu)
+        F[..., mu, :, :] = -(beta / 3.0) * traceless_hermitian(0.5j * (W - _dag(W)))
+    return F
+
+
+def expi(P, eps):
+    """exp(i eps P) for Hermitian P, from its eigen-decomposition."""
+    w, v = np.linalg.eigh(P)
+    return (v * np.exp(1j * eps * w)[..., None, :]) @ _dag(v)
+
+
+def kinetic(P):
+    return 0.5 * float(np.sum(np.real(np.einsum("...ij,...ji->...", P, P))))
+
+
+def _fermion(U, phi, kappa, bc, tol):
+    """X = (M^H M)^{-1} phi (FP64 CG), S_f = Re <phi, X> and the Lie-form force."""
+    X, _, _ = oracle.cg(U, phi, kappa, bc, system=0, tol=tol)
+    Y = oracle.apply_M(U, X, kappa, bc)
+    S = float(np.real(np.vdot(phi.ravel(), X.ravel())))
+    return S, oracle.force(U, X, Y, kappa, bc, mode=1)
+
+
+def hamiltonian_and_force(U, P, beta, phi=None, kappa=0.0, bc=None, tol=1e-12):
+    S = gauge_action(U, beta)
+    F = gauge_force(U, beta)
+    if phi is not None:
+        Sf, Ff = _fermion(U, phi, kappa, bc, tol)
+        S += Sf
+        F = F + Ff
+    return kinetic(P) + S, F
+
+
+def trajectory(U, P, beta, eps, nsteps, phi=None, kappa=0.0, bc=None, tol=1e-12):
+    """One leapfrog trajectory of nsteps steps of size eps.  Returns (U', P', H0, H1);
+    the inputs are not modified."""
+    U = U.copy()
+    P = P.copy()
+    H0, F = hamiltonian_and_force(U, P, beta, phi, kappa, bc, tol)
+    P -= 0.5 * eps * F
+    for k in range(nsteps):
+        U = np.einsum("...ij,...jk->...ik", expi(P, eps), U)
+        _, F = hamiltonian_and_force(U, P, beta, phi, kappa, bc, tol)
+        P -= (eps if k < nsteps - 1 else 0.5 * eps) * F
+    H1, _ = hamiltonian_and_force(U, P, beta, phi, kappa, bc, tol)
+    return U, P, H0, H1

@@ -152,6 +152,18 @@ class Synth:
         return self._complex_normal((nrhs, lt, lz, ly, lx, 4, 3), np.sqrt(0.5))
 
 
+    def momenta(self, dims) -> torch.Tensor:
+        """Traceless Hermitian Gaussian matrices per link with density exp(-Tr P^2 / 2),
+        shape (Lt,Lz,Ly,Lx,4,3,3): diagonal entries of variance 1, off-diagonal real and
+        imaginary parts of variance 1/2, then the trace removed."""
+        lx, ly, lz, lt = _check_dims(dims)
+        z = self._complex_normal((lt, lz, ly, lx, 4, 3, 3), np.sqrt(0.5))
+        h = (z + z.conj().transpose(-1, -2)) * np.sqrt(0.5)
+        tr = torch.diagonal(h, dim1=-2, dim2=-1).sum(-1)
+        eye = torch.eye(3, dtype=C128, device=self.device)
+        return h - tr[..., None, None] / 3 * eye
+
+
 def unit_gauge(dims, device="cpu") -> torch.Tensor:
     lx, ly, lz, lt = _check_dims(dims)
     u = torch.zeros((lt, lz, ly, lx, 4, 3, 3), dtype=C128, device=device)

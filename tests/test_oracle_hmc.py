@@ -1,0 +1,100 @@
+"""Pins of the HMC oracle (gauge action and force, link update, leapfrog trajectory).
+
+Gauge force: central finite differences of the plaquette action along a random
+Lie-algebra direction on every link (the perturbation by scipy's expm, a route
+that never touches the oracle's force or exponential).  Action: zero on the unit
+field and the closed form of a constant abelian flux.  Link update: unitary and
+equal to scipy's expm.  Trajectory: reversibility (flip P, integrate back) and
+the leapfrog's O(eps^2) energy violation (halving eps quarters Delta H), with
+and without the pseudofermion term.
+"""
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+from oracle import hmc
+from paper_2302_00850_amd.synth import Synth, bc_phases, unit_gauge
+
+DIMS = (4, 4, 4, 4)
+ANTI = bc_phases((0, 0, 0, np.pi))
+
+
+@pytest.fixture(scope="module")
+def field():
+    s = Synth(41)
+    U = s.gauge(DIMS, mix=0.5).numpy()
+    P = s.momenta(DIMS).numpy()
+    H = s.momenta(DIMS).numpy()
+    phi = s.gaussian_spinor(DIMS).numpy()[0]
+    return U, P, H, phi
+
+
+def _expm_field(H, d):
+    flat = H.reshape(-1, 3, 3)
+    return np.stack([expm(1j * d * h) for h in flat]).reshape(H.shape)
+
+
+def test_gauge_action_closed_forms():
+    U = unit_gauge(DIMS).numpy()
+    assert hmc.gauge_action(U, 5.7) == 0.0
+    # one flux quantum per colour in the x-y plane: every x-y plaquette is
+    # diag(e^{i f}, e^{-i f}, 1), every other plaquette 1
+    lx, ly = DIMS[0], DIMS[1]
+    f = 2 * np.pi / (lx * ly)
+    x = np.arange(lx)[None, None, None, :]
+    y = np.arange(ly)[None, None, :, None]
+    th_y = np.broadcast_to(f * x, U.shape[:4])
+    th_x = np.broadcast_to(np.where(x == lx - 1, -f * lx * y, 0.0 * y), U.shape[:4])
+    for mu, th in ((1, th_y), (0, th_x)):
+        U[..., mu, 0, 0] = np.exp(1j * th)
+        U[..., mu, 1, 1] = np.exp(-1j * th)
+    V = int(np.prod(DIMS))
+    beta = 6.0
+    want = beta * V * (1 - (2 * np.cos(f) + 1) / 3)
+    assert hmc.gauge_action(U, beta) == pytest.approx(want, rel=1e-13)
+
+
+def test_gauge_force_matches_finite_difference(field):
+    U, P, H, phi = field
+    beta, d = 5.5, 1e-5
+    F = hmc.gauge_force(U, beta)
+    assert np.abs(F - np.conj(np.swapaxes(F, -1, -2))).max() < 1e-14
+    assert np.abs(np.einsum("...ii->...", F)).max() < 1e-14
+    up = np.einsum("...ij,...jk->...ik", _expm_field(H, d), U)
+    dn = np.einsum("...ij,...jk->...ik", _expm_field(H, -d), U)
+    fd = (hmc.gauge_action(up, beta) - hmc.gauge_action(dn, beta)) / (2 * d)
+    an = float(np.sum(np.real(np.einsum("...ij,...ji->...", H, F))))
+    assert an == pytest.approx(fd, rel=1e-7)
+
+
+def test_link_update_is_unitary_expm(field):
+    U, P, H, phi = field
+    E = hmc.expi(P, 0.37)
+    np.testing.assert_allclose(E, _expm_field(P, 0.37), atol=1e-13)
+    eye = np.broadcast_to(np.eye(3), E.shape)
+    assert np.abs(E @ np.conj(np.swapaxes(E, -1, -2)) - eye).max() < 1e-14
+    assert hmc.kinetic(P) == pytest.approx(0.5 * np.sum(np.abs(P) ** 2), rel=1e-13)
+
+
+@pytest.mark.parametrize("fermions", [False, True])
+def test_trajectory_reversible(field, fermions):
+    U, P, H, phi = field
+    kw = dict(phi=phi, kappa=0.12, bc=ANTI, tol=1e-14) if fermions else {}
+    U1, P1, H0, H1 = hmc.trajectory(U, P, 5.5, 0.05, 6, **kw)
+    U2, P2, H1b, H2 = hmc.trajectory(U1, -P1, 5.5, 0.05, 6, **kw)
+    assert np.abs(U2 - U).max() < 1e-10
+    assert np.abs(P2 + P).max() < 1e-9
+    assert H2 == pytest.approx(H0, abs=1e-8)
+
+
+@pytest.mark.parametrize("fermions", [False, True])
+def test_trajectory_energy_violation_is_second_order(field, fermions):
+    U, P, H, phi = field
+    kw = dict(phi=phi, kappa=0.12, bc=ANTI, tol=1e-14) if fermions else {}
+    dH = []
+    for n in (4, 8, 16):
+        _, _, H0, H1 = hmc.trajectory(U, P, 5.5, 0.4 / n, n, **kw)
+        dH.append(abs(H1 - H0))
+    assert dH[0] > 1e-6
+    for a, b in zip(dH, dH[1:]):
+        assert 3.0 < a / b < 5.0, dH
