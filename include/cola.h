@@ -208,6 +208,55 @@ int cola_cg_solve(cola_handle_t *h, void *x, const void *b, int nrhs, const cola
 int cola_fermion_force(cola_handle_t *h, void *F_dev, const void *X_dev, const void *Y_dev,
                        int mode, void *stream);
 
+/* -------------------------------------------------------------------- HMC */
+/* Hybrid Monte Carlo (the paper's gauge-field generation algorithm, after Duane et al.,
+ * in its list of algorithms) for SU(3) links with the Wilson plaquette action
+ *   S_g = beta sum_{x, mu<nu} (1 - Re Tr U_mu,nu(x) / 3)
+ * plus, when a pseudofermion phi is given, S_f = phi^H (M^H M)^{-1} phi for plain Wilson
+ * M (the handle's kappa and boundary phases).  Momenta P are traceless Hermitian per
+ * link, H = sum Tr(P^2) / 2 + S_g + S_f, links move as U -> exp(i eps P) U and the
+ * forces are in the COLA_FORCE_LIE form.  U, P and F are canonical complex128 device
+ * arrays [Lt][Lz][Ly][Lx][4][3][3]; phi a canonical spinor.  All asynchronous on
+ * `stream` unless stated. */
+
+/* F = force of S_g (traceless Hermitian, dS_g/de = Tr(H F) along U -> e^{ieH} U). */
+int cola_gauge_force(cola_handle_t *h, void *F_dev, const void *U_dev, double beta,
+                     void *stream);
+/* *S = S_g(U) (host double); synchronises `stream`. */
+int cola_gauge_action(cola_handle_t *h, const void *U_dev, double beta, double *S,
+                      void *stream);
+/* U <- exp(i eps P) U on every link (in place). */
+int cola_link_update(cola_handle_t *h, void *U_dev, const void *P_dev, double eps, void *stream);
+/* P -= eps (F1 + F2) on every link (F2 may be NULL). */
+int cola_momentum_update(cola_handle_t *h, void *P_dev, const void *F1_dev, const void *F2_dev,
+                         double eps, void *stream);
+
+typedef struct {
+    double beta;     /* gauge coupling                                              */
+    double eps;      /* molecular-dynamics step size                                */
+    int nsteps;      /* leapfrog steps (trajectory length eps * nsteps)             */
+    double cg_tol;   /* FP64 CG tolerance of the fermion solves (phi given)        */
+    int cg_max_iter; /* cap per solve                                               */
+} cola_hmc_params_t;
+
+typedef struct {
+    int status;           /* COLA_OK, or COLA_NOT_CONVERGED if a fermion solve failed */
+    double H0, H1;        /* Hamiltonian before and after                             */
+    double dH;            /* H1 - H0 (Metropolis: accept with probability min(1, e^-dH)) */
+    double kinetic0, kinetic1, gauge0, gauge1, fermion0, fermion1; /* parts of H0, H1   */
+    int cg_iterations;    /* summed over the nsteps + 1 fermion solves                */
+    double seconds;       /* wall time                                                */
+} cola_hmc_result_t;
+
+/* One leapfrog trajectory (half step in P, nsteps alternating link and momentum steps,
+ * half step in P) in place on U and P; phi = NULL for the pure gauge theory.  The
+ * accept/reject decision is the caller's (it keeps a copy of U and draws the uniform
+ * number).  With phi: needs csw = 0, re-packs the handle's gauge field from U at every
+ * step (cola_set_gauge) and leaves it packed from the final U.  Returns COLA_EINVAL for
+ * nsteps < 1, eps <= 0 or non-finite parameters.  Synchronises `stream`. */
+int cola_hmc_trajectory(cola_handle_t *h, void *U_dev, void *P_dev, const void *phi_dev,
+                        const cola_hmc_params_t *p, cola_hmc_result_t *r, void *stream);
+
 /* ---------------------------------------------------------- diagnostics */
 
 int cola_get_stats(cola_handle_t *h, cola_stats_t *s); /* synchronises pending timings */

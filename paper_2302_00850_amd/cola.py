@@ -52,6 +52,20 @@ class CgResult(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+class HmcParams(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("eps", ctypes.c_double), ("nsteps", ctypes.c_int),
+                ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int)]
+
+
+class HmcResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("H0", ctypes.c_double), ("H1", ctypes.c_double),
+                ("dH", ctypes.c_double), ("kinetic0", ctypes.c_double),
+                ("kinetic1", ctypes.c_double), ("gauge0", ctypes.c_double),
+                ("gauge1", ctypes.c_double), ("fermion0", ctypes.c_double),
+                ("fermion1", ctypes.c_double), ("cg_iterations", ctypes.c_int),
+                ("seconds", ctypes.c_double)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("hop_launches", ctypes.c_longlong * 4), ("hop_seconds", ctypes.c_double * 4),
                 ("hop_bytes", ctypes.c_double * 4), ("hop_flops", ctypes.c_double * 4)]
@@ -60,7 +74,9 @@ class Stats(ctypes.Structure):
 EXPORTS = ["cola_abi_version", "cola_create", "cola_destroy", "cola_last_error", "cola_set_gauge",
            "cola_gauge_is_su3", "cola_field_bytes", "cola_pack_spinor", "cola_unpack_spinor",
            "cola_dslash_apply", "cola_cg_solve", "cola_fermion_force", "cola_get_stats",
-           "cola_reset_stats", "cola_set_tuning", "cola_tune_dump"]
+           "cola_reset_stats", "cola_set_tuning", "cola_tune_dump", "cola_gauge_force",
+           "cola_gauge_action", "cola_link_update", "cola_momentum_update",
+           "cola_hmc_trajectory"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -96,6 +112,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cola_set_tuning.argtypes = [_vp, ctypes.c_int]
     lib.cola_tune_dump.argtypes = [_vp, ctypes.c_char_p, ctypes.c_size_t]
     lib.cola_tune_dump.restype = ctypes.c_size_t
+    lib.cola_gauge_force.argtypes = [_vp, _vp, _vp, ctypes.c_double, _vp]
+    lib.cola_gauge_action.argtypes = [_vp, _vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                      _vp]
+    lib.cola_link_update.argtypes = [_vp, _vp, _vp, ctypes.c_double, _vp]
+    lib.cola_momentum_update.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp]
+    lib.cola_hmc_trajectory.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(HmcParams),
+                                        ctypes.POINTER(HmcResult), _vp]
     _lib = lib
     return lib
 
@@ -162,6 +185,29 @@ def cola_cg_solve(h, x, b, nrhs, params: CgParams, result: CgResult, stream=None
 
 def cola_fermion_force(h, F, X, Y, mode, stream=None):
     return _check(h, load().cola_fermion_force(h, F, X, Y, mode, stream))
+
+
+def cola_gauge_force(h, F, U, beta, stream=None):
+    return _check(h, load().cola_gauge_force(h, F, U, float(beta), stream))
+
+
+def cola_gauge_action(h, U, beta, stream=None) -> float:
+    S = ctypes.c_double()
+    _check(h, load().cola_gauge_action(h, U, float(beta), ctypes.byref(S), stream))
+    return S.value
+
+
+def cola_link_update(h, U, P, eps, stream=None):
+    return _check(h, load().cola_link_update(h, U, P, float(eps), stream))
+
+
+def cola_momentum_update(h, P, F1, F2, eps, stream=None):
+    return _check(h, load().cola_momentum_update(h, P, F1, F2, float(eps), stream))
+
+
+def cola_hmc_trajectory(h, U, P, phi, params: HmcParams, result: HmcResult, stream=None):
+    return _check(h, load().cola_hmc_trajectory(h, U, P, phi, ctypes.byref(params),
+                                                 ctypes.byref(result), stream))
 
 
 def cola_get_stats(h) -> Stats:
@@ -304,6 +350,50 @@ class Lattice:
         cola_fermion_force(self.h, _ptr(F), _ptr(X.contiguous()), _ptr(Y.contiguous()), mode,
                            _stream())
         return F
+
+    # ------------------------------------------------------------------ HMC
+    def _gauge_like(self, A: torch.Tensor, name: str):
+        if A.dtype != torch.complex128 or tuple(A.shape) != self.site_shape + (4, 3, 3) \
+                or not A.is_contiguous() or not A.is_cuda:
+            raise ValueError(f"{name} must be contiguous complex128 (Lt,Lz,Ly,Lx,4,3,3) on the GPU")
+
+    def gauge_force(self, U: torch.Tensor, beta: float) -> torch.Tensor:
+        self._gauge_like(U, "U")
+        F = torch.empty_like(U)
+        cola_gauge_force(self.h, _ptr(F), _ptr(U), beta, _stream())
+        return F
+
+    def gauge_action(self, U: torch.Tensor, beta: float) -> float:
+        self._gauge_like(U, "U")
+        return cola_gauge_action(self.h, _ptr(U), beta, _stream())
+
+    def link_update(self, U: torch.Tensor, P: torch.Tensor, eps: float):
+        """U <- exp(i eps P) U in place."""
+        self._gauge_like(U, "U")
+        self._gauge_like(P, "P")
+        cola_link_update(self.h, _ptr(U), _ptr(P), eps, _stream())
+
+    def momentum_update(self, P: torch.Tensor, F1: torch.Tensor, eps: float, F2=None):
+        """P -= eps (F1 + F2) in place."""
+        for A, n in ((P, "P"), (F1, "F1")) + (((F2, "F2"),) if F2 is not None else ()):
+            self._gauge_like(A, n)
+        cola_momentum_update(self.h, _ptr(P), _ptr(F1), _ptr(F2) if F2 is not None else None,
+                             eps, _stream())
+
+    def hmc_trajectory(self, U: torch.Tensor, P: torch.Tensor, beta: float, eps: float,
+                       nsteps: int, phi=None, cg_tol=1e-12, cg_max_iter=20000) -> dict:
+        """One leapfrog trajectory in place on U and P (phi: pseudofermion or None)."""
+        self._gauge_like(U, "U")
+        self._gauge_like(P, "P")
+        if phi is not None:
+            if self._spinor_rhs(phi) != 1:
+                raise ValueError("phi must be one canonical spinor")
+            phi = phi.contiguous()
+        prm = HmcParams(float(beta), float(eps), int(nsteps), float(cg_tol), int(cg_max_iter))
+        r = HmcResult()
+        cola_hmc_trajectory(self.h, _ptr(U), _ptr(P), _ptr(phi) if phi is not None else None,
+                            prm, r, _stream())
+        return {k: getattr(r, k) for k, _ in HmcResult._fields_}
 
     def stats(self, prec=None) -> dict:
         """Hop accounting for one precision, or summed over all when prec is None."""

@@ -1,0 +1,351 @@
+// Kernels of the HMC molecular-dynamics step (hybrid Monte Carlo: the gauge-field
+// generation algorithm the paper lists, after Duane et al.) on canonical FP64 fields
+// U[site][mu][3][3] and traceless Hermitian momenta P of the same layout:
+//
+//   gauge force   F_mu(x) = -(beta/3) P_TH[i (W - W^H) / 2],  W = U_mu(x) A_mu(x), A the
+//                 sum of the six staples, so that dS_g/de = Tr(H F) along
+//                 U -> exp(i e H) U for S_g = beta sum_plaq (1 - Re Tr U_plaq / 3)
+//   momentum      P -= eps (F1 + F2)
+//   link update   U <- exp(i eps P) U (scaling and squaring of a Taylor series)
+//   reductions    sum of Re Tr U_plaq, sum of Tr P^2, Re <a, b>: per-block partials
+//                 in a fixed-shape LDS tree, then the block-order reduce launch.
+//
+// One lane per link (or per site for the plaquette sum), grid-stride loops.
+#include "device.h"
+#include "launch.h"
+
+namespace cola {
+
+namespace {
+
+using C = cpx<double>;
+
+// grid cap of the grid-stride kernels (also the partial count of their reductions)
+constexpr int kHmcGrid = 4096;
+static_assert(kHmcGrid <= kRedMaxBlocks, "reduction partials");
+
+struct M3 {
+    C a[3][3];
+};
+
+__device__ __forceinline__ C conj(C a) { return {a.x, -a.y}; }
+
+__device__ __forceinline__ M3 ld3(const C *p) {
+    M3 m;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) m.a[i][j] = p[3 * i + j];
+    return m;
+}
+
+__device__ __forceinline__ void st3(C *p, const M3 &m) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) p[3 * i + j] = m.a[i][j];
+}
+
+// A B, A B^H, A^H B
+__device__ __forceinline__ M3 mm(const M3 &A, const M3 &B) {
+    M3 r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            C s = cmul(A.a[i][0], B.a[0][j]);
+            s = cmadd(s, A.a[i][1], B.a[1][j]);
+            r.a[i][j] = cmadd(s, A.a[i][2], B.a[2][j]);
+        }
+    return r;
+}
+__device__ __forceinline__ M3 mmd(const M3 &A, const M3 &B) {
+    M3 r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            C s = cmul(A.a[i][0], conj(B.a[j][0]));
+            s = cmadd(s, A.a[i][1], conj(B.a[j][1]));
+            r.a[i][j] = cmadd(s, A.a[i][2], conj(B.a[j][2]));
+        }
+    return r;
+}
+__device__ __forceinline__ M3 mdm(const M3 &A, const M3 &B) {
+    M3 r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            C s = cmul(conj(A.a[0][i]), B.a[0][j]);
+            s = cmadd(s, conj(A.a[1][i]), B.a[1][j]);
+            r.a[i][j] = cmadd(s, conj(A.a[2][i]), B.a[2][j]);
+        }
+    return r;
+}
+
+__device__ __forceinline__ void coords(const Geom &g, uint32_t s, int x[4]) {
+    uint32_t q = s;
+    x[0] = (int)(q % (uint32_t)g.L[0]);
+    q /= (uint32_t)g.L[0];
+    x[1] = (int)(q % (uint32_t)g.L[1]);
+    q /= (uint32_t)g.L[1];
+    x[2] = (int)(q % (uint32_t)g.L[2]);
+    x[3] = (int)(q / (uint32_t)g.L[2]);
+}
+
+// lexicographic site of x + d mu (d = +-1), periodic
+__device__ __forceinline__ uint32_t step(const Geom &g, const int x[4], int mu, int d,
+                                         int y[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) y[k] = x[k];
+    y[mu] += d;
+    if (y[mu] == g.L[mu]) y[mu] = 0;
+    if (y[mu] < 0) y[mu] = g.L[mu] - 1;
+    return (uint32_t)(y[0] + g.L[0] * (y[1] + g.L[1] * (y[2] + g.L[2] * y[3])));
+}
+
+__device__ __forceinline__ const C *link(const C *U, uint32_t s, int mu) {
+    return U + ((size_t)s * 4 + (size_t)mu) * 9;
+}
+
+__global__ void __launch_bounds__(256) gauge_force_kernel(const Geom g, const C *__restrict__ U,
+                                                          C *__restrict__ F, double beta) {
+    const uint32_t V = 2u * (uint32_t)g.Vh;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < 4u * V;
+         t += gridDim.x * blockDim.x) {
+        const uint32_t s = t >> 2;
+        const int mu = (int)(t & 3u);
+        int x[4], y[4], z[4];
+        coords(g, s, x);
+        const uint32_t sp = step(g, x, mu, 1, y);  // x + mu
+        M3 A;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) A.a[i][j] = C{0.0, 0.0};
+        for (int nu = 0; nu < 4; ++nu) {
+            if (nu == mu) continue;
+            int w[4];
+            const uint32_t sn = step(g, x, nu, 1, w);    // x + nu
+            const uint32_t sm = step(g, x, nu, -1, w);   // x - nu
+            const uint32_t spm = step(g, y, nu, -1, z);  // x + mu - nu
+            // upper: U_nu(x+mu) U_mu(x+nu)^H U_nu(x)^H
+            const M3 up =
+                mmd(mmd(ld3(link(U, sp, nu)), ld3(link(U, sn, mu))), ld3(link(U, s, nu)));
+            // lower: U_nu(x+mu-nu)^H U_mu(x-nu)^H U_nu(x-nu)
+            const M3 a1 = ld3(link(U, spm, nu));
+            const M3 a2 = ld3(link(U, sm, mu));
+            const M3 a3 = ld3(link(U, sm, nu));
+            // a1^H a2^H a3 = (a2 a1)^H a3
+            const M3 low = mdm(mm(a2, a1), a3);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    A.a[i][j] = {A.a[i][j].x + up.a[i][j].x + low.a[i][j].x,
+                                 A.a[i][j].y + up.a[i][j].y + low.a[i][j].y};
+        }
+        const M3 W = mm(ld3(link(U, s, mu)), A);
+        // X = i (W - W^H) / 2, traceless, times -(beta / 3)
+        M3 X;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const C d = {W.a[i][j].x - W.a[j][i].x, W.a[i][j].y + W.a[j][i].y};
+                X.a[i][j] = {-0.5 * d.y, 0.5 * d.x};  // i d / 2
+            }
+        const double tr = (X.a[0][0].x + X.a[1][1].x + X.a[2][2].x) / 3.0;
+        const double f = -beta / 3.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            X.a[i][i].x -= tr;
+            X.a[i][i].y = 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) X.a[i][j] = {f * X.a[i][j].x, f * X.a[i][j].y};
+        }
+        st3(F + (size_t)t * 9, X);
+    }
+}
+
+__global__ void __launch_bounds__(256) momentum_kernel(C *__restrict__ P,
+                                                       const C *__restrict__ F1,
+                                                       const C *__restrict__ F2, double eps,
+                                                       size_t n) {
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (size_t)gridDim.x * blockDim.x) {
+        C f = F1[k];
+        if (F2) f = {f.x + F2[k].x, f.y + F2[k].y};
+        P[k] = {fma(-eps, f.x, P[k].x), fma(-eps, f.y, P[k].y)};
+    }
+}
+
+// exp(X) for X = i eps P: halve until the 1-norm is at most 1/2, Taylor series to 16th
+// order (truncation below 1e-19 there), square back.
+__device__ __forceinline__ M3 expi3(const M3 &P, double eps) {
+    M3 X;
+    double nrm = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        double c = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            X.a[i][j] = {-eps * P.a[i][j].y, eps * P.a[i][j].x};
+            c += sqrt(X.a[i][j].x * X.a[i][j].x + X.a[i][j].y * X.a[i][j].y);
+        }
+        nrm = fmax(nrm, c);
+    }
+    int sq = 0;
+    double scale = 1.0;
+    while (nrm * scale > 0.5 && sq < 60) {
+        scale *= 0.5;
+        ++sq;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) X.a[i][j] = {scale * X.a[i][j].x, scale * X.a[i][j].y};
+    // Horner: E = I + X/1 (I + X/2 (I + ... (I + X/16)))
+    M3 E;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) E.a[i][j] = {i == j ? 1.0 : 0.0, 0.0};
+    for (int k = 16; k >= 1; --k) {
+        M3 T = mm(X, E);
+        const double r = 1.0 / k;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                E.a[i][j] = {(i == j ? 1.0 : 0.0) + r * T.a[i][j].x, r * T.a[i][j].y};
+    }
+    for (int k = 0; k < sq; ++k) E = mm(E, E);
+    return E;
+}
+
+__global__ void __launch_bounds__(256) link_update_kernel(C *__restrict__ U,
+                                                          const C *__restrict__ P, double eps,
+                                                          size_t nlinks) {
+    for (size_t l = (size_t)blockIdx.x * blockDim.x + threadIdx.x; l < nlinks;
+         l += (size_t)gridDim.x * blockDim.x) {
+        const M3 E = expi3(ld3(P + l * 9), eps);
+        st3(U + l * 9, mm(E, ld3(U + l * 9)));
+    }
+}
+
+// fixed-shape LDS tree over the 256 lanes of a block; lane 0 writes the partial
+__device__ __forceinline__ void block_partial(double v, double *partial) {
+    __shared__ double red[256];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) plaquette_kernel(const Geom g, const C *__restrict__ U,
+                                                        double *__restrict__ partial) {
+    const uint32_t V = 2u * (uint32_t)g.Vh;
+    double acc = 0.0;
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < V;
+         s += gridDim.x * blockDim.x) {
+        int x[4], y[4], z[4];
+        coords(g, s, x);
+        for (int mu = 0; mu < 4; ++mu) {
+            const uint32_t sp = step(g, x, mu, 1, y);
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                const uint32_t sn = step(g, x, nu, 1, z);
+                // Re Tr U_mu(x) U_nu(x+mu) U_mu(x+nu)^H U_nu(x)^H
+                const M3 a = mm(ld3(link(U, s, mu)), ld3(link(U, sp, nu)));
+                const M3 c = mmd(a, ld3(link(U, sn, mu)));
+                const M3 d = mmd(c, ld3(link(U, s, nu)));
+                acc += d.a[0][0].x + d.a[1][1].x + d.a[2][2].x;
+            }
+        }
+    }
+    block_partial(acc, partial);
+}
+
+__global__ void __launch_bounds__(256) sqnorm_kernel(const C *__restrict__ a, size_t n,
+                                                     double *__restrict__ partial) {
+    double acc = 0.0;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (size_t)gridDim.x * blockDim.x)
+        acc = fma(a[k].x, a[k].x, fma(a[k].y, a[k].y, acc));
+    block_partial(acc, partial);
+}
+
+__global__ void __launch_bounds__(256) redot_kernel(const C *__restrict__ a,
+                                                    const C *__restrict__ b, size_t n,
+                                                    double *__restrict__ partial) {
+    double acc = 0.0;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (size_t)gridDim.x * blockDim.x)
+        acc = fma(a[k].x, b[k].x, fma(a[k].y, b[k].y, acc));
+    block_partial(acc, partial);
+}
+
+int grid_for(size_t n) {
+    const size_t g = (n + 255) / 256;
+    return (int)std::max<size_t>(1, std::min<size_t>(g, kHmcGrid));
+}
+
+}  // namespace
+
+hipError_t launch_gauge_force(const Geom &g, const void *U, void *F, double beta,
+                              hipStream_t st) {
+    const size_t n = (size_t)8 * g.Vh;
+    hipLaunchKernelGGL(gauge_force_kernel, dim3(grid_for(n)), dim3(256), 0, st, g,
+                       (const C *)U, (C *)F, beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_momentum_update(void *P, const void *F1, const void *F2, double eps,
+                                  size_t nlinks, hipStream_t st) {
+    const size_t n = nlinks * 9;
+    hipLaunchKernelGGL(momentum_kernel, dim3(grid_for(n)), dim3(256), 0, st, (C *)P,
+                       (const C *)F1, (const C *)F2, eps, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_link_update(void *U, const void *P, double eps, size_t nlinks,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(link_update_kernel, dim3(grid_for(nlinks)), dim3(256), 0, st, (C *)U,
+                       (const C *)P, eps, nlinks);
+    return hipGetLastError();
+}
+
+hipError_t launch_plaquette_sum(const Geom &g, const void *U, double *partial, double *result,
+                                hipStream_t st) {
+    const int grid = grid_for((size_t)2 * g.Vh);
+    hipLaunchKernelGGL(plaquette_kernel, dim3(grid), dim3(256), 0, st, g, (const C *)U,
+                       partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce_partials(partial, grid, 1, result, st);
+}
+
+hipError_t launch_sqnorm(const void *a, size_t n, double *partial, double *result,
+                         hipStream_t st) {
+    const int grid = grid_for(n);
+    hipLaunchKernelGGL(sqnorm_kernel, dim3(grid), dim3(256), 0, st, (const C *)a, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce_partials(partial, grid, 1, result, st);
+}
+
+hipError_t launch_redot(const void *a, const void *b, size_t n, double *partial, double *result,
+                        hipStream_t st) {
+    const int grid = grid_for(n);
+    hipLaunchKernelGGL(redot_kernel, dim3(grid), dim3(256), 0, st, (const C *)a, (const C *)b, n,
+                       partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce_partials(partial, grid, 1, result, st);
+}
+
+}  // namespace cola

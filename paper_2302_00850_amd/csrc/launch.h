@@ -91,4 +91,22 @@ hipError_t launch_clover_build(const Geom &g, const void *U, double kappa, doubl
 hipError_t launch_force(const Geom &g, const void *gauge64_18, const void *X, const void *Y,
                         void *F, double kappa, const Cplx64 phase[4], int mode, hipStream_t st);
 
+// --- HMC (canonical FP64 fields; one lane per link)
+// F = traceless Hermitian force of the Wilson plaquette action with coupling beta
+hipError_t launch_gauge_force(const Geom &g, const void *U, void *F, double beta, hipStream_t st);
+// P -= eps (F1 + F2) over nlinks 3x3 matrices (F2 may be null)
+hipError_t launch_momentum_update(void *P, const void *F1, const void *F2, double eps,
+                                  size_t nlinks, hipStream_t st);
+// U <- exp(i eps P) U over nlinks links
+hipError_t launch_link_update(void *U, const void *P, double eps, size_t nlinks, hipStream_t st);
+// *result (device) = sum over sites and mu < nu of Re Tr U_plaq
+hipError_t launch_plaquette_sum(const Geom &g, const void *U, double *partial, double *result,
+                                hipStream_t st);
+// *result = sum |a_k|^2 over n complex entries
+hipError_t launch_sqnorm(const void *a, size_t n, double *partial, double *result,
+                         hipStream_t st);
+// *result = Re sum conj(a_k) b_k over n complex entries
+hipError_t launch_redot(const void *a, const void *b, size_t n, double *partial, double *result,
+                        hipStream_t st);
+
 }  // namespace cola
