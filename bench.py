@@ -219,6 +219,52 @@ def workloads_mode(args):
                           "solve_seconds": info["seconds"], "iterations": info["iterations"],
                           "force_ms": fms, "force_GBs": fbytes / fms / 1e6}), flush=True)
         lat.close()
+    if "hmc" in sel:
+        # one HMC trajectory (leapfrog) with one pseudofermion on the force lattice, and
+        # the gauge-force and link-update kernels timed alone
+        dims = (24, 24, 24, 48)
+        beta, eps, nsteps = 5.6, 0.02, 10
+        s = Synth(0, device="cuda")
+        U = s.gauge(dims)
+        P = s.momenta(dims)
+        eta = s.gaussian_spinor(dims, 1)
+        lat = cola.Lattice(dims, KAPPA, bc, 0.0)
+        lat.set_gauge(U)
+        ep = lat.pack(eta, cola.COLA_FP64, -1)
+        pp = lat.empty_packed(cola.COLA_FP64, 1, -1)
+        lat.dslash(pp, ep, cola.COLA_OP_MDAG, -1, cola.COLA_FP64, 1)
+        phi = lat.unpack(pp, cola.COLA_FP64, 1, -1)[0]
+        U0, P0 = U.clone(), P.clone()
+        lat.hmc_trajectory(U, P, beta, eps, 2, phi=phi, cg_tol=1e-10)  # warm
+        U.copy_(U0)
+        P.copy_(P0)
+        torch.cuda.synchronize()
+        info = lat.hmc_trajectory(U, P, beta, eps, nsteps, phi=phi, cg_tol=1e-10)
+        V = int(np.prod(dims))
+        nl = 4 * V
+        F = lat.gauge_force(U, beta)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        for _ in range(10):
+            lat.gauge_force(U, beta)
+        ev[1].record()
+        for _ in range(10):
+            lat.link_update(U, F, 1e-3)
+        ev[2].record()
+        torch.cuda.synchronize()
+        gms = ev[0].elapsed_time(ev[1]) / 10
+        lms = ev[1].elapsed_time(ev[2]) / 10
+        # gauge force: every link read once (staples share them through the caches) and
+        # the force written: 2 x 144 B per link; link update: P and U read, U written
+        print(json.dumps({"workload": "hmc_24x24x24x48", "lattice": list(dims), "beta": beta,
+                          "kappa": KAPPA, "eps": eps, "nsteps": nsteps,
+                          "trajectory_seconds": info["seconds"], "dH": info["dH"],
+                          "H0": info["H0"], "cg_iterations": info["cg_iterations"],
+                          "status": info["status"],
+                          "gauge_force_ms": gms, "gauge_force_GBs": nl * 288 / gms / 1e6,
+                          "link_update_ms": lms, "link_update_GBs": nl * 432 / lms / 1e6}),
+              flush=True)
+        lat.close()
     if "clover" in sel:
         dims = (48, 48, 48, 96)
         s = Synth(0, device="cuda", rng="torch")
@@ -278,8 +324,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--mode", default="solve", choices=["solve", "hop", "copy", "workloads"])
-    ap.add_argument("--workloads", default="mixed,force,clover",
-                    help="workloads mode: any of mixed, force, clover")
+    ap.add_argument("--workloads", default="mixed,force,clover,hmc",
+                    help="workloads mode: any of mixed, force, clover, hmc")
     ap.add_argument("--block", type=int, default=0, help="use block CG in the multi-RHS solves")
     ap.add_argument("--lattice", default="32,32,32,64", help="hop mode: Lx,Ly,Lz,Lt")
     ap.add_argument("--prec", default="0,2,3", help="hop mode: precisions (0 FP64 .. 3 FP16)")
