@@ -195,9 +195,10 @@ int cola_dslash_apply(cola_handle_t *h, void *out, const void *in, int op, int p
  * [nrhs][Lt][Lz][Ly][Lx][4][3].  For COLA_SYS_SCHUR only the even sites of b are
  * read and the odd sites of x are set to zero.  Synchronises `stream`.  Returns
  * COLA_OK, COLA_NOT_CONVERGED (x = best iterate) or COLA_BREAKDOWN, or < 0.
- * On the even-odd systems the CG update of x and r runs inside the last hop of
- * S^dag S (A p is never stored); the environment variable COLA_CG_FUSE=0 selects a
- * separate update kernel instead (same iterates up to the order of the |r|^2 sums). */
+ * The CG update of x and r runs inside the last hop of S^dag S (even-odd systems) or
+ * the two parity hops of M^dag (full lattice), so A p is never stored; the environment
+ * variable COLA_CG_FUSE=0 selects a separate update kernel instead (same iterates up to
+ * the order of the |r|^2 sums). */
 int cola_cg_solve(cola_handle_t *h, void *x, const void *b, int nrhs, const cola_cg_params_t *p,
                   cola_cg_result_t *r, void *stream);
 

@@ -320,6 +320,18 @@ BlasShape blas_shape(const Geom &g, int nrhs, int nblk) {
         case SpinorFmt::F16: { constexpr SpinorFmt FT = SpinorFmt::F16; __VA_ARGS__; } break; \
     }
 
+namespace {
+__global__ void scalar_add_kernel(double *a, const double *b, int n) {
+    const int i = (int)threadIdx.x;
+    if (i < n) a[i] += b[i];
+}
+}  // namespace
+
+hipError_t launch_scalar_add(double *a, const double *b, int n, hipStream_t st) {
+    hipLaunchKernelGGL(scalar_add_kernel, dim3(1), dim3(64), 0, st, a, b, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_cg_xr(const BlasShape &b, SpinorFmt fx, SpinorFmt fp, SpinorFmt fr,
                         SpinorFmt fap, void *x, const void *p, void *r, const void *ap,
                         const double *rho, const double *pi, const double *pi2,

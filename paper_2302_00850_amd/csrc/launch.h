@@ -43,6 +43,8 @@ BlasShape blas_shape(const Geom &g, int nrhs, int nblk);
 
 // x += alpha p, r -= alpha Ap, result = |r|^2 ;
 // alpha_q = active_q ? rho_q / (pi_q + pi2_q) : 0   (pi2 may be null)
+// a[i] += b[i] for i < n <= 64 (per-rhs scalars)
+hipError_t launch_scalar_add(double *a, const double *b, int n, hipStream_t st);
 hipError_t launch_cg_xr(const BlasShape &b, SpinorFmt fx, SpinorFmt fp, SpinorFmt fr,
                         SpinorFmt fap, void *x, const void *p, void *r, const void *ap,
                         const double *rho, const double *pi, const double *pi2,

@@ -33,7 +33,17 @@ namespace cola {
 
 namespace {
 
-enum Slot { RHO = 0, RHO_NEW = 1, PI = 2, PI2 = 3, BNORM = 4, SCALE = 5, TRUE_RES = 6, TMP = 7 };
+enum Slot {
+    RHO = 0,
+    RHO_NEW = 1,
+    PI = 2,
+    PI2 = 3,
+    BNORM = 4,
+    SCALE = 5,
+    TRUE_RES = 6,
+    TMP = 7,
+    RHO_EVEN = 8  // |r|^2 of the even block (full-lattice fused CG step)
+};
 
 struct Ctx {
     cola_handle_t *h;
@@ -77,14 +87,57 @@ int normal(const Ctx &c, int prec, void *out, const void *in) {
 }
 
 // One CG step: Ap = A p, pi = <p, Ap>, then x += alpha p, r -= alpha Ap and
-// rho_new = |r|^2.  On the even-odd system with x, r and p in the operator's storage the
-// update runs inside the last hop (Ap is never stored); COLA_CG_FUSE=0 selects the
-// separate update kernel.
+// rho_new = |r|^2.  With x, r and p in the operator's storage the update runs inside the
+// last hops (Ap is never stored): the last hop of S^dag S on the even-odd system, the two
+// parity hops of M^dag on the full lattice; COLA_CG_FUSE=0 selects the separate update
+// kernel.
+int full_normal_cg_step(const Ctx &c, int prec, void *x, void *r, void *pv) {
+    cola_handle_t *h = c.h;
+    const SpinorFmt sf = spinor_fmt(prec);
+    const size_t bb = spinor_block_bytes(h->g, sf, c.R);
+    void *t;
+    COLA_TRY(get_vec(h, "cg_full_t_" + std::to_string((int)sf) + "_" + std::to_string(c.R),
+                     2 * bb, &t));
+    const bool clover = h->csw != 0.0;
+    const void *A = sf == SpinorFmt::F64 ? h->clov64 : h->clov32;
+    auto blk = [bb](const void *base, int q) { return (char *)base + q * bb; };
+    // t = M p, |t_e|^2 -> PI, |t_o|^2 -> PI2
+    for (int q = 0; q < 2; ++q) {
+        HopCall hc{blk(t, q), blk(pv, 1 - q), q, 0};
+        hc.epi = clover ? EPI_CLOV_XPAY : EPI_XPAY;
+        hc.x = blk(pv, q);
+        hc.a = -h->kappa;
+        hc.clov = A;
+        hc.norm_result = c.slot(q == 0 ? PI : PI2);
+        COLA_TRY(hop(h, hc, prec, c.R, c.st));
+    }
+    // per parity: the M^dag hop with the update of x and r; |r_e|^2 + |r_o|^2 -> RHO_NEW
+    for (int q = 0; q < 2; ++q) {
+        HopCall hc{blk(r, q), blk(t, 1 - q), q, 1};
+        hc.epi = clover ? EPI_CLOV_XPAY_CG : EPI_XPAY_CG;
+        hc.x = blk(t, q);
+        hc.a = -h->kappa;
+        hc.clov = A;
+        hc.norm_result = c.slot(q == 0 ? RHO_EVEN : RHO_NEW);
+        hc.cg_x = blk(x, q);
+        hc.cg_r = blk(r, q);
+        hc.cg_p = blk(pv, q);
+        hc.cg_rho = c.slot(RHO);
+        hc.cg_pi = c.slot(PI);
+        hc.cg_pi2 = c.slot(PI2);
+        hc.cg_active = h->active;
+        COLA_TRY(hop(h, hc, prec, c.R, c.st));
+    }
+    COLA_HIP(h, launch_scalar_add(c.slot(RHO_NEW), c.slot(RHO_EVEN), c.R, c.st));
+    return COLA_OK;
+}
+
 int cg_step(const Ctx &c, int prec, SpinorFmt fx, void *x, void *r, void *pv, void *ap) {
     cola_handle_t *h = c.h;
     const SpinorFmt fp = spinor_fmt(prec);
     const char *env = getenv("COLA_CG_FUSE");
-    const bool fuse = !c.full && fx == fp && !(env && env[0] == '0');
+    const bool fuse = fx == fp && !(env && env[0] == '0');
+    if (fuse && c.full) return full_normal_cg_step(c, prec, x, r, pv);
     if (fuse)
         return schur_normal_cg_step(h, prec, c.R, c.st, x, r, pv, c.slot(RHO), c.slot(PI),
                                     h->active, c.slot(RHO_NEW));

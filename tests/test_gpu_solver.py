@@ -57,8 +57,8 @@ def _normal_residual(U, x, b, system, kappa, bc, A=None, Ai=None):
     return rel(ax, be)
 
 
-@pytest.mark.parametrize("system,fuse", [(cola.COLA_SYS_MDAGM, "1"), (cola.COLA_SYS_SCHUR, "1"),
-                                         (cola.COLA_SYS_SCHUR, "0")])
+@pytest.mark.parametrize("system,fuse", [(cola.COLA_SYS_MDAGM, "1"), (cola.COLA_SYS_MDAGM, "0"),
+                                         (cola.COLA_SYS_SCHUR, "1"), (cola.COLA_SYS_SCHUR, "0")])
 def test_cg_fp64_fixed_iterations_match_oracle(fields, system, fuse, monkeypatch):
     """fuse: the even-odd CG update inside the last hop (1) or as its own kernel (0)."""
     monkeypatch.setenv("COLA_CG_FUSE", fuse)
@@ -158,10 +158,12 @@ def test_cg_clover_schur(fields, scheme):
 
 @pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("csw", [0.0, 1.0])
-def test_cg_fused_update_matches_separate(fields, scheme, csw, monkeypatch):
-    """The CG update fused into the last hop of S^dag S against the separate update
-    kernel: both reach the tolerance, in about as many iterations, at the same
-    solutions (to the tolerance times the condition number)."""
+@pytest.mark.parametrize("system", [cola.COLA_SYS_SCHUR, cola.COLA_SYS_MDAGM])
+def test_cg_fused_update_matches_separate(fields, scheme, csw, system, monkeypatch):
+    """The CG update fused into the last hop of S^dag S (even-odd) or the two parity
+    hops of M^dag (full lattice) against the separate update kernel: both reach the
+    tolerance, in about as many iterations, at the same solutions (to the tolerance
+    times the condition number)."""
     U, b = fields
     kappa = 0.118 if csw else KAPPA
     A = oracle.clover(U, kappa, csw) if csw else None
@@ -171,12 +173,12 @@ def test_cg_fused_update_matches_separate(fields, scheme, csw, monkeypatch):
     out = {}
     for fuse in ("0", "1"):
         monkeypatch.setenv("COLA_CG_FUSE", fuse)
-        x, info = lat.cg(_cuda(src), system=cola.COLA_SYS_SCHUR, scheme=scheme, tol=1e-10)
+        x, info = lat.cg(_cuda(src), system=system, scheme=scheme, tol=1e-10)
         assert info["status"] == cola.COLA_OK, (fuse, info)
         out[fuse] = (x.cpu().numpy(), info)
     xs = out["1"][0]
     for q in range(12):
-        r = _normal_residual(U, xs[q], src[q], cola.COLA_SYS_SCHUR, kappa, ANTI, A, Ai)
+        r = _normal_residual(U, xs[q], src[q], system, kappa, ANTI, A, Ai)
         assert r <= 1.05e-10, (q, r)
     n0, n1 = out["0"][1]["iterations"], out["1"][1]["iterations"]
     assert abs(n1 - n0) <= max(2, n0 // 10), (n0, n1)
