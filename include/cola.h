@@ -202,6 +202,20 @@ int cola_dslash_apply(cola_handle_t *h, void *out, const void *in, int op, int p
 int cola_cg_solve(cola_handle_t *h, void *x, const void *b, int nrhs, const cola_cg_params_t *p,
                   cola_cg_result_t *r, void *stream);
 
+/* Multi-shift CG (the shifted solves of rational HMC, Kennedy et al. in the paper's
+ * list of algorithms): (A + shifts[q]) x_q = b for q < nshift (1 .. 16, shifts >= 0)
+ * from one Krylov space, A = M^H M (COLA_SYS_MDAGM) or S^H S on the even sites
+ * (COLA_SYS_SCHUR), FP64 only (p->scheme = COLA_CG_FP64, p->block = 0).  b: one canonical
+ * complex128 spinor; x: canonical [nshift][Lt][Lz][Ly][Lx][4][3] (SCHUR: odd sites set
+ * to zero).  A shift stops when its iterated residual reaches p->tol |b|; status is
+ * COLA_NOT_CONVERGED if a true residual exceeds 2 p->tol |b| (the iterated and true
+ * residuals differ by rounding).  r->iterations counts the shared iterations,
+ * r->true_rel_residual[q] (caller array of nshift) is |b - (A + sigma_q) x_q| / |b|.
+ * Returns like cola_cg_solve; COLA_EINVAL for other systems or schemes, nshift out of
+ * range or a negative shift.  Synchronises `stream`. */
+int cola_cg_multishift(cola_handle_t *h, void *x, const void *b, int nshift, const double *shifts,
+                       const cola_cg_params_t *p, cola_cg_result_t *r, void *stream);
+
 /* Fermion force of S = phi^H (M^H M)^{-1} phi for plain Wilson M, from X = (M^H M)^{-1} phi
  * and Y = M X (canonical complex128 spinors, nrhs = 1).  F: canonical gauge-shaped
  * complex128 output [Lt][Lz][Ly][Lx][4][3][3].  COLA_EINVAL when csw != 0 (the clover

@@ -76,7 +76,7 @@ EXPORTS = ["cola_abi_version", "cola_create", "cola_destroy", "cola_last_error",
            "cola_dslash_apply", "cola_cg_solve", "cola_fermion_force", "cola_get_stats",
            "cola_reset_stats", "cola_set_tuning", "cola_tune_dump", "cola_gauge_force",
            "cola_gauge_action", "cola_link_update", "cola_momentum_update",
-           "cola_hmc_trajectory"]
+           "cola_hmc_trajectory", "cola_cg_multishift"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -112,6 +112,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cola_set_tuning.argtypes = [_vp, ctypes.c_int]
     lib.cola_tune_dump.argtypes = [_vp, ctypes.c_char_p, ctypes.c_size_t]
     lib.cola_tune_dump.restype = ctypes.c_size_t
+    lib.cola_cg_multishift.argtypes = [_vp, _vp, _vp, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(CgParams),
+                                       ctypes.POINTER(CgResult), _vp]
     lib.cola_gauge_force.argtypes = [_vp, _vp, _vp, ctypes.c_double, _vp]
     lib.cola_gauge_action.argtypes = [_vp, _vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                       _vp]
@@ -185,6 +188,13 @@ def cola_cg_solve(h, x, b, nrhs, params: CgParams, result: CgResult, stream=None
 
 def cola_fermion_force(h, F, X, Y, mode, stream=None):
     return _check(h, load().cola_fermion_force(h, F, X, Y, mode, stream))
+
+
+def cola_cg_multishift(h, x, b, nshift, shifts, params: CgParams, result: CgResult,
+                       stream=None):
+    sh = (ctypes.c_double * nshift)(*[float(v) for v in shifts])
+    return _check(h, load().cola_cg_multishift(h, x, b, int(nshift), sh, ctypes.byref(params),
+                                               ctypes.byref(result), stream))
 
 
 def cola_gauge_force(h, F, U, beta, stream=None):
@@ -342,6 +352,22 @@ class Lattice:
                 "reliable_updates": r.reliable_updates, "true_rel_residual": list(res),
                 "seconds": r.seconds}
         return x, info
+
+    def cg_multishift(self, b: torch.Tensor, shifts, system=COLA_SYS_MDAGM, tol=1e-10,
+                      max_iter=20000):
+        """(A + shifts[q]) x_q = b for every shift from one Krylov space (FP64); returns
+        x with a leading shift axis and the solver info."""
+        if self._spinor_rhs(b) != 1:
+            raise ValueError("multi-shift CG takes one right-hand side")
+        n = len(shifts)
+        x = torch.zeros((n,) + self.site_shape + (4, 3), dtype=torch.complex128, device="cuda")
+        p = CgParams(system, COLA_CG_FP64, 0, tol, max_iter, 50, 0.0, 0, 0)
+        res = (ctypes.c_double * n)()
+        r = CgResult(0, 0, 0, 0, ctypes.cast(res, ctypes.POINTER(ctypes.c_double)), 0.0)
+        bc = b.reshape(self.site_shape + (4, 3)).contiguous()  # alive through the call
+        cola_cg_multishift(self.h, _ptr(x), _ptr(bc), n, shifts, p, r, _stream())
+        return x, {"status": r.status, "iterations": r.iterations,
+                   "true_rel_residual": list(res), "seconds": r.seconds}
 
     def force(self, X: torch.Tensor, Y: torch.Tensor, mode=COLA_FORCE_GRAD) -> torch.Tensor:
         if self._spinor_rhs(X) != 1 or self._spinor_rhs(Y) != 1:

@@ -11,6 +11,8 @@
 namespace cola {
 int cg_solve_impl(cola_handle_t *h, void *x, const void *b, int nrhs, const cola_cg_params_t *p,
                   cola_cg_result_t *r, hipStream_t st);
+int cg_multishift_impl(cola_handle_t *h, void *x, const void *b, int nshift, const double *sigma,
+                       const cola_cg_params_t *p, cola_cg_result_t *r, hipStream_t st);
 }
 
 using namespace cola;
@@ -238,6 +240,24 @@ int cola_cg_solve(cola_handle_t *h, void *x, const void *b, int nrhs, const cola
     if (p->scheme != COLA_CG_FP64 && !h->su3)
         return set_error(h, COLA_EINVAL, "mixed-precision schemes need an SU(3) gauge field");
     return cg_solve_impl(h, x, b, nrhs, p, r, as_stream(stream));
+}
+
+int cola_cg_multishift(cola_handle_t *h, void *x, const void *b, int nshift, const double *shifts,
+                       const cola_cg_params_t *p, cola_cg_result_t *r, void *stream) {
+    if (!h) return COLA_EINVAL;
+    if (!x || !b || !p || !shifts) return set_error(h, COLA_EINVAL, "null pointer");
+    if (nshift < 1 || nshift > kMaxRhs)
+        return set_error(h, COLA_EINVAL, "nshift must be 1 .. 16");
+    for (int q = 0; q < nshift; ++q)
+        if (!(shifts[q] >= 0.0) || !std::isfinite(shifts[q]))
+            return set_error(h, COLA_EINVAL, "shifts must be finite and >= 0");
+    if (p->system != COLA_SYS_MDAGM && p->system != COLA_SYS_SCHUR)
+        return set_error(h, COLA_EINVAL, "multi-shift CG runs on the MDAGM and SCHUR systems");
+    if (p->scheme != COLA_CG_FP64 || p->block)
+        return set_error(h, COLA_EINVAL, "multi-shift CG is FP64, lockstep");
+    if (!(p->tol > 0) || p->max_iter < 1) return set_error(h, COLA_EINVAL, "bad tol / max_iter");
+    if (!h->gauge_set) return set_error(h, COLA_ESTATE, "no gauge field set");
+    return cg_multishift_impl(h, x, b, nshift, shifts, p, r, as_stream(stream));
 }
 
 int cola_fermion_force(cola_handle_t *h, void *F, const void *X, const void *Y, int mode,

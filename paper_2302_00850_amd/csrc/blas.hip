@@ -321,11 +321,78 @@ BlasShape blas_shape(const Geom &g, int nrhs, int nblk) {
     }
 
 namespace {
+struct MsFn {
+    void *x, *p;
+    const void *r;
+    size_t bx, br;
+    MsCoef k;
+    int S, R;
+    __device__ double operator()(const Loc &l) const {
+        if (!k.active[l.r]) return 0.0;
+        const auto X = view<SpinorFmt::F64>(x, bx, l, S, R);
+        const auto P = view<SpinorFmt::F64>(p, bx, l, S, R);
+        const auto Rv = view<SpinorFmt::F64>(r, br, l, S, 1);
+        cpx<double> xv[12], pv[12], rv[12];
+        X.load(l.i, l.r, xv);
+        P.load(l.i, l.r, pv);
+        Rv.load(l.i, 0, rv);
+        const double a = k.alpha[l.r], z = k.zeta[l.r], b = k.beta[l.r];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            xv[c] = {fma(a, pv[c].x, xv[c].x), fma(a, pv[c].y, xv[c].y)};
+            pv[c] = {fma(z, rv[c].x, b * pv[c].x), fma(z, rv[c].y, b * pv[c].y)};
+        }
+        X.store(l.i, l.r, xv);
+        P.store(l.i, l.r, pv);
+        return 0.0;
+    }
+};
+
+struct MsResFn {
+    const void *b, *ax, *x;
+    size_t bb, bx;
+    double sigma[kRedMaxWidth];
+    int S, R;
+    __device__ double operator()(const Loc &l) const {
+        const auto B = view<SpinorFmt::F64>(b, bb, l, S, 1);
+        const auto AX = view<SpinorFmt::F64>(ax, bx, l, S, R);
+        const auto X = view<SpinorFmt::F64>(x, bx, l, S, R);
+        cpx<double> bv[12], av[12], xv[12];
+        B.load(l.i, 0, bv);
+        AX.load(l.i, l.r, av);
+        X.load(l.i, l.r, xv);
+        const double sg = sigma[l.r];
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const double re = bv[c].x - av[c].x - sg * xv[c].x;
+            const double im = bv[c].y - av[c].y - sg * xv[c].y;
+            s += re * re + im * im;
+        }
+        return s;
+    }
+};
+
 __global__ void scalar_add_kernel(double *a, const double *b, int n) {
     const int i = (int)threadIdx.x;
     if (i < n) a[i] += b[i];
 }
 }  // namespace
+
+hipError_t launch_ms_update(const BlasShape &sh, void *x, void *p, const void *r,
+                            const MsCoef &k, hipStream_t st) {
+    MsFn fn{x, p, r, block_bytes(SpinorFmt::F64, sh.S, sh.R), block_bytes(SpinorFmt::F64, sh.S, 1),
+            k, sh.S, sh.R};
+    return run(fn, sh, nullptr, st);
+}
+
+hipError_t launch_ms_residual(const BlasShape &sh, const void *b, const void *ax, const void *x,
+                              const double *sigma, const Reduce &red, hipStream_t st) {
+    MsResFn fn{b, ax, x, block_bytes(SpinorFmt::F64, sh.S, 1),
+               block_bytes(SpinorFmt::F64, sh.S, sh.R), {}, sh.S, sh.R};
+    for (int q = 0; q < sh.R && q < kRedMaxWidth; ++q) fn.sigma[q] = sigma[q];
+    return run(fn, sh, &red, st);
+}
 
 hipError_t launch_scalar_add(double *a, const double *b, int n, hipStream_t st) {
     hipLaunchKernelGGL(scalar_add_kernel, dim3(1), dim3(64), 0, st, a, b, n);

@@ -41,10 +41,22 @@ struct BlasShape {
 };
 BlasShape blas_shape(const Geom &g, int nrhs, int nblk);
 
-// x += alpha p, r -= alpha Ap, result = |r|^2 ;
-// alpha_q = active_q ? rho_q / (pi_q + pi2_q) : 0   (pi2 may be null)
+// Multi-shift CG, FP64, shifts as the rhs of the x and p fields (R = sh.R) and the
+// shared residual r a one-rhs field: for active shifts q,
+//   x_q += alpha_q p_q ;  p_q = zeta_q r + beta_q p_q
+struct MsCoef {
+    double alpha[kRedMaxWidth], zeta[kRedMaxWidth], beta[kRedMaxWidth];
+    int active[kRedMaxWidth];
+};
+hipError_t launch_ms_update(const BlasShape &sh, void *x, void *p, const void *r,
+                            const MsCoef &k, hipStream_t st);
+// result_q = |b - ax_q - sigma_q x_q|^2 (b a one-rhs field, ax and x with R = sh.R)
+hipError_t launch_ms_residual(const BlasShape &sh, const void *b, const void *ax, const void *x,
+                              const double *sigma, const Reduce &red, hipStream_t st);
 // a[i] += b[i] for i < n <= 64 (per-rhs scalars)
 hipError_t launch_scalar_add(double *a, const double *b, int n, hipStream_t st);
+// x += alpha p, r -= alpha Ap, result = |r|^2 ;
+// alpha_q = active_q ? rho_q / (pi_q + pi2_q) : 0   (pi2 may be null)
 hipError_t launch_cg_xr(const BlasShape &b, SpinorFmt fx, SpinorFmt fp, SpinorFmt fr,
                         SpinorFmt fap, void *x, const void *p, void *r, const void *ap,
                         const double *rho, const double *pi, const double *pi2,

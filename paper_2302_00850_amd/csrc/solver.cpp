@@ -741,4 +741,132 @@ int cg_solve_impl(cola_handle_t *h, void *x, const void *b, int nrhs, const cola
     return o.status;
 }
 
+// ---------------------------------------------------------------- multi-shift CG
+
+// (A + sigma_q) x_q = b for nshift shifts sigma_q >= 0 from the Krylov space of the
+// unshifted CG on A (M^H M or S^H S, FP64, one rhs).  The shifted residuals stay
+// collinear with the base residual, r_q = zeta_q r, and with the base CG's alpha, beta
+//   zeta_q' = zeta_q zeta_q^old alpha^old /
+//             (alpha beta^old (zeta_q^old - zeta_q) + zeta_q^old alpha^old (1 + sigma_q alpha))
+//   x_q += alpha zeta_q'/zeta_q p_q ;  p_q = zeta_q' r' + beta (zeta_q'/zeta_q)^2 p_q
+// (zeta = zeta^old = 1, alpha^old = 1, beta^old = 0, p_q = b at the start).  The
+// shifts' x and p live as the rhs of one packed field; the scalar recursion runs on
+// the host from the base alpha and beta read back each iteration.  A shift stops once
+// zeta_q^2 |r|^2 <= tol^2 |b|^2; its true residual is then checked against twice that.
+int cg_multishift_impl(cola_handle_t *h, void *x, const void *b, int nshift, const double *sigma,
+                       const cola_cg_params_t *p, cola_cg_result_t *res, hipStream_t st) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int full = p->system == COLA_SYS_MDAGM ? 1 : 0;
+    Ctx c{h, st, 1, full};
+    Ctx cn{h, st, nshift, full};
+    const BlasShape sh1 = c.shape(), shn = cn.shape();
+    void *b64, *r64, *p64, *ap, *xb, *xs, *ps, *axs;
+    COLA_TRY(vec(c, "b64", SpinorFmt::F64, &b64));
+    COLA_TRY(vec(c, "r64", SpinorFmt::F64, &r64));
+    COLA_TRY(vec(c, "ms_p", SpinorFmt::F64, &p64));
+    COLA_TRY(vec(c, "ms_ap", SpinorFmt::F64, &ap));
+    COLA_TRY(vec(c, "ms_xb", SpinorFmt::F64, &xb));
+    COLA_TRY(vec(cn, "ms_xs", SpinorFmt::F64, &xs));
+    COLA_TRY(vec(cn, "ms_ps", SpinorFmt::F64, &ps));
+    COLA_TRY(vec(cn, "ms_axs", SpinorFmt::F64, &axs));
+    COLA_HIP(h, launch_pack_spinor(h->g, SpinorFmt::F64, b64, b, 1, full ? -1 : 0, st));
+    const size_t b1 = c.bytes(SpinorFmt::F64), bn_ = cn.bytes(SpinorFmt::F64);
+    COLA_HIP(h, hipMemcpyAsync(r64, b64, b1, hipMemcpyDeviceToDevice, st));
+    COLA_HIP(h, hipMemcpyAsync(p64, b64, b1, hipMemcpyDeviceToDevice, st));
+    COLA_HIP(h, hipMemsetAsync(xb, 0, b1, st));
+    COLA_HIP(h, hipMemsetAsync(xs, 0, bn_, st));
+    COLA_HIP(h, hipMemsetAsync(ps, 0, bn_, st));
+    // p_q = b: the update with alpha = 0, zeta = 1, beta = 0
+    MsCoef k{};
+    for (int q = 0; q < nshift; ++q) k.zeta[q] = 1.0, k.active[q] = 1;
+    COLA_HIP(h, launch_ms_update(shn, xs, ps, r64, k, st));
+    COLA_HIP(h, launch_norm2(sh1, SpinorFmt::F64, b64, reduce_into(h, BNORM), st));
+    double bnorm = 0.0;
+    COLA_TRY(read_slot(c, BNORM, &bnorm));
+    COLA_HIP(h, hipMemcpyAsync(c.slot(RHO), c.slot(BNORM), sizeof(double),
+                               hipMemcpyDeviceToDevice, st));
+    if (full) COLA_TRY(zero_pi2(c));
+    COLA_TRY(write_active(c, std::vector<int>{1}));
+    const double thr = p->tol * p->tol * bnorm;
+    std::vector<double> zeta(nshift, 1.0), zold(nshift, 1.0), zn(nshift);
+    std::vector<int> done(nshift, bnorm == 0.0 ? 1 : 0);
+    double alpha_old = 1.0, beta_old = 0.0, rho = bnorm;
+    int status = COLA_OK, it = 0;
+    auto all_done = [&] {
+        for (int q = 0; q < nshift; ++q)
+            if (!done[q]) return false;
+        return true;
+    };
+    while (!all_done()) {
+        if (it >= p->max_iter) {
+            status = COLA_NOT_CONVERGED;
+            break;
+        }
+        COLA_TRY(normal(c, COLA_FP64, ap, p64));
+        COLA_HIP(h, launch_cg_xr(sh1, SpinorFmt::F64, SpinorFmt::F64, SpinorFmt::F64,
+                                 SpinorFmt::F64, xb, p64, r64, ap, c.slot(RHO), c.slot(PI),
+                                 full ? c.slot(PI2) : nullptr, h->active,
+                                 reduce_into(h, RHO_NEW), st));
+        double pi = 0.0, pi2 = 0.0, rho_new = 0.0;
+        COLA_TRY(read_slot(c, PI, &pi));
+        if (full) COLA_TRY(read_slot(c, PI2, &pi2));
+        COLA_TRY(read_slot(c, RHO_NEW, &rho_new));
+        const double alpha = rho / (pi + pi2), beta = rho_new / rho;
+        if (!std::isfinite(alpha) || !std::isfinite(beta) || !(pi + pi2 > 0.0)) {
+            status = COLA_BREAKDOWN;
+            break;
+        }
+        for (int q = 0; q < nshift; ++q) {
+            k.active[q] = !done[q];
+            if (done[q]) {  // frozen (its zeta may underflow from here on)
+                zn[q] = zeta[q];
+                continue;
+            }
+            zn[q] = zeta[q] * zold[q] * alpha_old /
+                    (alpha * beta_old * (zold[q] - zeta[q]) +
+                     zold[q] * alpha_old * (1.0 + sigma[q] * alpha));
+            k.alpha[q] = alpha * zn[q] / zeta[q];
+            k.zeta[q] = zn[q];
+            k.beta[q] = beta * (zn[q] / zeta[q]) * (zn[q] / zeta[q]);
+            if (!std::isfinite(zn[q])) status = COLA_BREAKDOWN;
+        }
+        if (status != COLA_OK) break;
+        COLA_HIP(h, launch_ms_update(shn, xs, ps, r64, k, st));
+        COLA_HIP(h, launch_cg_p(sh1, SpinorFmt::F64, SpinorFmt::F64, r64, p64, c.slot(RHO_NEW),
+                                c.slot(RHO), h->active, st));
+        COLA_TRY(rotate_rho(c));
+        zold = zeta;
+        zeta = zn;
+        alpha_old = alpha;
+        beta_old = beta;
+        rho = rho_new;
+        ++it;
+        for (int q = 0; q < nshift; ++q)
+            if (zeta[q] * zeta[q] * rho <= thr) done[q] = 1;
+    }
+    // true residuals |b - (A + sigma_q) x_q| / |b|, all shifts in one multi-rhs pass
+    std::vector<double> tr(nshift, 0.0);
+    COLA_TRY(normal(cn, COLA_FP64, axs, xs));
+    COLA_HIP(h, launch_ms_residual(shn, b64, axs, xs, sigma, reduce_into(h, TRUE_RES), st));
+    COLA_TRY(read_slot(cn, TRUE_RES, tr.data()));
+    // the recursive residuals drift from the true ones by rounding: a shift counts as
+    // converged within twice the tolerance
+    for (int q = 0; q < nshift; ++q)
+        if (!(tr[q] <= 4.0 * thr) && status == COLA_OK) status = COLA_NOT_CONVERGED;
+    if (!full) COLA_HIP(h, hipMemsetAsync(x, 0, (size_t)h->g.Vh * 2 * 12 * 16 * nshift, st));
+    COLA_HIP(h, launch_unpack_spinor(h->g, SpinorFmt::F64, x, xs, nshift, full ? -1 : 0, st));
+    COLA_HIP(h, hipStreamSynchronize(st));
+    if (res) {
+        res->status = status;
+        res->iterations = it;
+        res->outer_cycles = 0;
+        res->reliable_updates = 0;
+        if (res->true_rel_residual)
+            for (int q = 0; q < nshift; ++q)
+                res->true_rel_residual[q] = bnorm > 0 ? std::sqrt(tr[q] / bnorm) : 0.0;
+        res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}
+
 }  // namespace cola
