@@ -265,6 +265,28 @@ def workloads_mode(args):
                           "link_update_ms": lms, "link_update_GBs": nl * 432 / lms / 1e6}),
               flush=True)
         lat.close()
+    if "multishift" in sel:
+        # 12 shifts of the even-odd normal system (a rational-approximation-like spread)
+        # against one unshifted FP64 CG on the benchmark lattice
+        dims = (32, 32, 32, 64)
+        shifts = [0.0] + list(np.geomspace(1e-3, 3.0, 11))
+        s = Synth(0, device="cuda", rng="torch")
+        U = s.gauge(dims)
+        b = s.gaussian_spinor(dims, 1)[0]
+        lat = cola.Lattice(dims, KAPPA, bc, 0.0, cola.COLA_FLAG_TIMING)
+        lat.set_gauge(U)
+        lat.cg_multishift(b, shifts, system=cola.COLA_SYS_SCHUR, tol=TOL)  # warm
+        torch.cuda.synchronize()
+        x, ims = lat.cg_multishift(b, shifts, system=cola.COLA_SYS_SCHUR, tol=TOL)
+        _, i1 = solve(lat, b, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP64, tol=TOL)
+        print(json.dumps({"workload": "multishift_eo_32x32x32x64_12shifts", "lattice": list(dims),
+                          "shifts": shifts, "seconds": ims["seconds"],
+                          "iterations": ims["iterations"], "status": ims["status"],
+                          "max_true_rel_residual": max(ims["true_rel_residual"]),
+                          "unshifted_cg_seconds": i1["seconds"],
+                          "unshifted_cg_iterations": i1["iterations"],
+                          "cost_vs_one_solve": ims["seconds"] / i1["seconds"]}), flush=True)
+        lat.close()
     if "clover" in sel:
         dims = (48, 48, 48, 96)
         s = Synth(0, device="cuda", rng="torch")
@@ -324,8 +346,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--mode", default="solve", choices=["solve", "hop", "copy", "workloads"])
-    ap.add_argument("--workloads", default="mixed,force,clover,hmc",
-                    help="workloads mode: any of mixed, force, clover, hmc")
+    ap.add_argument("--workloads", default="mixed,force,clover,hmc,multishift",
+                    help="workloads mode: any of mixed, force, clover, hmc, multishift")
     ap.add_argument("--block", type=int, default=0, help="use block CG in the multi-RHS solves")
     ap.add_argument("--lattice", default="32,32,32,64", help="hop mode: Lx,Ly,Lz,Lt")
     ap.add_argument("--prec", default="0,2,3", help="hop mode: precisions (0 FP64 .. 3 FP16)")
