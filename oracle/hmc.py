@@ -8,6 +8,7 @@ pseudofermion field:
   H(U, P) = sum_links Tr(P^2) / 2 + S_g(U) + S_f(U)
   S_g = beta sum_{x, mu<nu} (1 - Re Tr U_mu,nu(x) / 3)       (plaquette action)
   S_f = phi^H (M^H M)^{-1} phi                               (M = 1 - kappa D)
+     or phi_e^H (S^H S)^{-1} phi_e on the even sites          (S = 1 - kappa^2 D_eo D_oe)
 
 P is traceless Hermitian per link.  A link moves as U -> exp(i eps P) U and the
 force F(U) is the traceless Hermitian matrix with dS/de = Tr(H F) along
@@ -101,26 +102,42 @@ def _fermion(U, phi, kappa, bc, tol):
     return S, oracle.force(U, X, Y, kappa, bc, mode=1)
 
 
-def hamiltonian_and_force(U, P, beta, phi=None, kappa=0.0, bc=None, tol=1e-12):
+def _fermion_eo(U, phi, kappa, bc, tol):
+    """Even-odd pseudofermion S_f = phi_e^H (S^H S)^{-1} phi_e, S = 1 - kappa^2 D_eo D_oe.
+
+    With X_e = (S^H S)^{-1} phi_e and Y_e = S X_e, dS_f = 2 kappa^2 Re[Y_e^H dD_eo X_o +
+    Y_o^H dD_oe X_e] for X_o = D_oe X_e and Y_o = (D_eo)^H Y_e: the full-lattice fermion
+    force of the vectors (X_e, X_o), (Y_e, Y_o) with kappa^2 in place of kappa."""
+    even = oracle.parity_mask(U.shape[:4][::-1])[..., None, None]
+    X, _, _ = oracle.cg(U, phi, kappa, bc, system=1, tol=tol)
+    X = np.where(even, X, 0)
+    S = float(np.real(np.vdot(np.where(even, phi, 0).ravel(), X.ravel())))
+    Y = np.where(even, oracle.apply_schur(U, X, kappa, bc), 0)
+    Xf = X + np.where(even, 0, oracle.hop(U, X, bc))
+    Yf = Y + np.where(even, 0, oracle.hop(U, Y, bc, dagger=True))
+    return S, oracle.force(U, Xf, Yf, kappa * kappa, bc, mode=1)
+
+
+def hamiltonian_and_force(U, P, beta, phi=None, kappa=0.0, bc=None, tol=1e-12, eo=False):
     S = gauge_action(U, beta)
     F = gauge_force(U, beta)
     if phi is not None:
-        Sf, Ff = _fermion(U, phi, kappa, bc, tol)
+        Sf, Ff = (_fermion_eo if eo else _fermion)(U, phi, kappa, bc, tol)
         S += Sf
         F = F + Ff
     return kinetic(P) + S, F
 
 
-def trajectory(U, P, beta, eps, nsteps, phi=None, kappa=0.0, bc=None, tol=1e-12):
+def trajectory(U, P, beta, eps, nsteps, phi=None, kappa=0.0, bc=None, tol=1e-12, eo=False):
     """One leapfrog trajectory of nsteps steps of size eps.  Returns (U', P', H0, H1);
-    the inputs are not modified."""
+    the inputs are not modified.  eo: the even-odd pseudofermion action."""
     U = U.copy()
     P = P.copy()
-    H0, F = hamiltonian_and_force(U, P, beta, phi, kappa, bc, tol)
+    H0, F = hamiltonian_and_force(U, P, beta, phi, kappa, bc, tol, eo)
     P -= 0.5 * eps * F
     for k in range(nsteps):
         U = np.einsum("...ij,...jk->...ik", expi(P, eps), U)
-        _, F = hamiltonian_and_force(U, P, beta, phi, kappa, bc, tol)
+        _, F = hamiltonian_and_force(U, P, beta, phi, kappa, bc, tol, eo)
         P -= (eps if k < nsteps - 1 else 0.5 * eps) * F
-    H1, _ = hamiltonian_and_force(U, P, beta, phi, kappa, bc, tol)
+    H1, _ = hamiltonian_and_force(U, P, beta, phi, kappa, bc, tol, eo)
     return U, P, H0, H1

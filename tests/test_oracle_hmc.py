@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 from scipy.linalg import expm
 
+import oracle
 from oracle import hmc
 from paper_2302_00850_amd.synth import Synth, bc_phases, unit_gauge
 
@@ -76,6 +77,27 @@ def test_link_update_is_unitary_expm(field):
     assert hmc.kinetic(P) == pytest.approx(0.5 * np.sum(np.abs(P) ** 2), rel=1e-13)
 
 
+def test_even_odd_fermion_force_matches_finite_difference(field):
+    """Even-odd pseudofermion: the force against central differences of
+    S_f = phi_e^H (S^H S)^{-1} phi_e computed by the oracle's Schur-system CG."""
+    U, P, H, phi = field
+    kappa, d = 0.12, 1e-5
+    even = oracle.parity_mask(DIMS)[..., None, None]
+
+    def action(V):
+        X, _, _ = oracle.cg(V, phi, kappa, ANTI, system=1, tol=1e-14)
+        return float(np.real(np.vdot(np.where(even, phi, 0).ravel(),
+                                     np.where(even, X, 0).ravel())))
+
+    S0, F = hmc._fermion_eo(U, phi, kappa, ANTI, 1e-14)
+    assert S0 == pytest.approx(action(U), rel=1e-12)
+    up = np.einsum("...ij,...jk->...ik", _expm_field(H, d), U)
+    dn = np.einsum("...ij,...jk->...ik", _expm_field(H, -d), U)
+    fd = (action(up) - action(dn)) / (2 * d)
+    an = float(np.sum(np.real(np.einsum("...ij,...ji->...", H, F))))
+    assert an == pytest.approx(fd, rel=1e-6)
+
+
 @pytest.mark.parametrize("fermions", [False, True])
 def test_trajectory_reversible(field, fermions):
     U, P, H, phi = field
@@ -87,10 +109,10 @@ def test_trajectory_reversible(field, fermions):
     assert H2 == pytest.approx(H0, abs=1e-8)
 
 
-@pytest.mark.parametrize("fermions", [False, True])
+@pytest.mark.parametrize("fermions", [False, True, "eo"])
 def test_trajectory_energy_violation_is_second_order(field, fermions):
     U, P, H, phi = field
-    kw = dict(phi=phi, kappa=0.12, bc=ANTI, tol=1e-14) if fermions else {}
+    kw = dict(phi=phi, kappa=0.12, bc=ANTI, tol=1e-14, eo=fermions == "eo") if fermions else {}
     dH = []
     for n in (4, 8, 16):
         _, _, H0, H1 = hmc.trajectory(U, P, 5.5, 0.4 / n, n, **kw)
