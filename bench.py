@@ -240,6 +240,18 @@ def workloads_mode(args):
         P.copy_(P0)
         torch.cuda.synchronize()
         info = lat.hmc_trajectory(U, P, beta, eps, nsteps, phi=phi, cg_tol=1e-10)
+        # the same with the even-odd pseudofermion (phi_e = S^H eta_e)
+        ee = lat.pack(eta, cola.COLA_FP64, 0)
+        pe = lat.empty_packed(cola.COLA_FP64, 1, 0)
+        lat.dslash(pe, ee, cola.COLA_OP_SCHUR_DAG, 0, cola.COLA_FP64, 1)
+        phi_e = lat.unpack(pe, cola.COLA_FP64, 1, 0)[0]
+        U.copy_(U0)
+        P.copy_(P0)
+        lat.hmc_trajectory(U, P, beta, eps, 2, phi=phi_e, cg_tol=1e-10, eo=True)  # warm
+        U.copy_(U0)
+        P.copy_(P0)
+        torch.cuda.synchronize()
+        ieo = lat.hmc_trajectory(U, P, beta, eps, nsteps, phi=phi_e, cg_tol=1e-10, eo=True)
         V = int(np.prod(dims))
         nl = 4 * V
         F = lat.gauge_force(U, beta)
@@ -261,6 +273,9 @@ def workloads_mode(args):
                           "trajectory_seconds": info["seconds"], "dH": info["dH"],
                           "H0": info["H0"], "cg_iterations": info["cg_iterations"],
                           "status": info["status"],
+                          "eo": {"trajectory_seconds": ieo["seconds"], "dH": ieo["dH"],
+                                 "cg_iterations": ieo["cg_iterations"],
+                                 "status": ieo["status"]},
                           "gauge_force_ms": gms, "gauge_force_GBs": nl * 288 / gms / 1e6,
                           "link_update_ms": lms, "link_update_GBs": nl * 432 / lms / 1e6}),
               flush=True)

@@ -252,6 +252,9 @@ typedef struct {
     int nsteps;      /* leapfrog steps (trajectory length eps * nsteps)             */
     double cg_tol;   /* FP64 CG tolerance of the fermion solves (phi given)        */
     int cg_max_iter; /* cap per solve                                               */
+    int eo;          /* 1: even-odd pseudofermion S_f = phi_e^H (S^H S)^{-1} phi_e,
+                        S = 1 - kappa^2 D_eo D_oe, phi's odd sites ignored (its solves
+                        run on the half lattice); 0: phi^H (M^H M)^{-1} phi            */
 } cola_hmc_params_t;
 
 typedef struct {

@@ -54,7 +54,7 @@ class CgResult(ctypes.Structure):
 
 class HmcParams(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("eps", ctypes.c_double), ("nsteps", ctypes.c_int),
-                ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int)]
+                ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int), ("eo", ctypes.c_int)]
 
 
 class HmcResult(ctypes.Structure):
@@ -407,15 +407,17 @@ class Lattice:
                              eps, _stream())
 
     def hmc_trajectory(self, U: torch.Tensor, P: torch.Tensor, beta: float, eps: float,
-                       nsteps: int, phi=None, cg_tol=1e-12, cg_max_iter=20000) -> dict:
-        """One leapfrog trajectory in place on U and P (phi: pseudofermion or None)."""
+                       nsteps: int, phi=None, cg_tol=1e-12, cg_max_iter=20000, eo=False) -> dict:
+        """One leapfrog trajectory in place on U and P (phi: pseudofermion or None; eo:
+        the even-odd pseudofermion action)."""
         self._gauge_like(U, "U")
         self._gauge_like(P, "P")
         if phi is not None:
             if self._spinor_rhs(phi) != 1:
                 raise ValueError("phi must be one canonical spinor")
             phi = phi.contiguous()
-        prm = HmcParams(float(beta), float(eps), int(nsteps), float(cg_tol), int(cg_max_iter))
+        prm = HmcParams(float(beta), float(eps), int(nsteps), float(cg_tol), int(cg_max_iter),
+                        1 if eo else 0)
         r = HmcResult()
         cola_hmc_trajectory(self.h, _ptr(U), _ptr(P), _ptr(phi) if phi is not None else None,
                             prm, r, _stream())

@@ -52,6 +52,46 @@ double read_scalar(cola_handle_t *h, const double *d, hipStream_t st, int *rc) {
     return v;
 }
 
+// Even-odd pseudofermion S_f = phi_e^H (S^H S)^{-1} phi_e (plain Wilson): with
+// X_e = (S^H S)^{-1} phi_e and Y_e = S X_e,
+//   dS_f = 2 kappa^2 Re[Y_e^H dD_eo X_o + Y_o^H dD_oe X_e],  X_o = D_oe X_e, Y_o = D_eo^H Y_e,
+// which is the full-lattice fermion force of (X_e, X_o) and (Y_e, Y_o) with kappa^2 in
+// place of kappa.  The handle's gauge field is already packed from U.
+int forces_eo(cola_handle_t *h, const void *phi, const cola_hmc_params_t *p, HmcWork &w,
+              bool first, bool energy, double *sf, int *iters, int *status, hipStream_t st) {
+    cola_cg_params_t cp{};
+    cp.system = COLA_SYS_SCHUR;
+    cp.scheme = COLA_CG_FP64;
+    cp.tol = p->cg_tol;
+    cp.max_iter = p->cg_max_iter;
+    cp.reliable_interval = 50;
+    cp.use_x0 = first ? 0 : 1;
+    double res = 0.0;
+    cola_cg_result_t cr{};
+    cr.true_rel_residual = &res;
+    COLA_TRY(cola_cg_solve(h, w.X, phi, 1, &cp, &cr, st));  // odd sites of X set to 0
+    *iters += cr.iterations;
+    if (cr.status != COLA_OK) *status = COLA_NOT_CONVERGED;
+    const size_t blk = cola_field_bytes(h, COLA_FP64, 1, 0);
+    char *xe = (char *)w.Xp, *xo = xe + blk, *ye = (char *)w.Yp, *yo = ye + blk;
+    COLA_TRY(cola_pack_spinor(h, w.Xp, w.X, COLA_FP64, 1, -1, st));
+    COLA_TRY(cola_dslash_apply(h, xo, xe, COLA_OP_HOP, 1, COLA_FP64, 1, st));
+    COLA_TRY(cola_dslash_apply(h, ye, xe, COLA_OP_SCHUR, 0, COLA_FP64, 1, st));
+    COLA_TRY(cola_dslash_apply(h, yo, ye, COLA_OP_HOP_DAG, 1, COLA_FP64, 1, st));
+    COLA_TRY(cola_unpack_spinor(h, w.Y, w.Yp, COLA_FP64, 1, -1, st));
+    if (energy) {
+        // X still has zero odd sites here: Re <phi, X> = Re <phi_e, X_e>
+        COLA_HIP(h, launch_redot(phi, w.X, (size_t)2 * h->g.Vh * 12, h->partial, w.sc + 1, st));
+        int rc = COLA_OK;
+        *sf = read_scalar(h, w.sc + 1, st, &rc);
+        COLA_TRY(rc);
+    }
+    COLA_TRY(cola_unpack_spinor(h, w.X, w.Xp, COLA_FP64, 1, -1, st));
+    COLA_HIP(h, launch_force(h->g, h->gauge[0], w.X, w.Y, w.Ff, h->kappa * h->kappa, h->phase,
+                             COLA_FORCE_LIE, st));
+    return COLA_OK;
+}
+
 // Forces at the current U into w.Fg (and w.Ff with fermions); with `energy`, the parts
 // of H that depend on U: *sg = S_g, *sf = S_f = Re <phi, X>.  X of the previous call is
 // the CG's starting guess.
@@ -71,6 +111,7 @@ int forces(cola_handle_t *h, void *U, const void *phi, const cola_hmc_params_t *
         return COLA_OK;
     }
     COLA_TRY(cola_set_gauge(h, U, st));
+    if (p->eo) return forces_eo(h, phi, p, w, first, energy, sf, iters, status, st);
     cola_cg_params_t cp{};
     cp.system = COLA_SYS_MDAGM;
     cp.scheme = COLA_CG_FP64;

@@ -70,31 +70,34 @@ def test_momentum_update(inputs):
     np.testing.assert_allclose(Pd.cpu().numpy(), P - 0.3 * (F1 + Q), rtol=0, atol=1e-14)
 
 
-@pytest.mark.parametrize("fermions", [False, True])
+@pytest.mark.parametrize("fermions", [False, True, "eo"])
 def test_trajectory_matches_oracle(inputs, fermions):
+    """fermions: none, the full-lattice pseudofermion, or the even-odd one."""
     U, P, Q, phi = inputs
     lat = _lat()
-    kw = dict(phi=phi, kappa=0.12, bc=ANTI, tol=1e-13) if fermions else {}
+    eo = fermions == "eo"
+    kw = dict(phi=phi, kappa=0.12, bc=ANTI, tol=1e-13, eo=eo) if fermions else {}
     U1, P1, H0, H1 = hmc.trajectory(U, P, BETA, 0.05, 5, **kw)
     Ud, Pd = _cuda(U), _cuda(P)
     info = lat.hmc_trajectory(Ud, Pd, BETA, 0.05, 5, phi=_cuda(phi) if fermions else None,
-                              cg_tol=1e-13)
+                              cg_tol=1e-13, eo=eo)
     assert info["status"] == cola.COLA_OK, info
     assert np.abs(Ud.cpu().numpy() - U1).max() < 1e-10
     assert np.abs(Pd.cpu().numpy() - P1).max() < 1e-9
     assert info["H0"] == pytest.approx(H0, rel=1e-11)
     assert info["H1"] == pytest.approx(H1, rel=1e-11)
     assert info["dH"] == pytest.approx(H1 - H0, abs=1e-7)
-    assert (info["cg_iterations"] > 0) == fermions
+    assert (info["cg_iterations"] > 0) == bool(fermions)
 
 
-def test_trajectory_reversible(inputs):
+@pytest.mark.parametrize("eo", [False, True])
+def test_trajectory_reversible(inputs, eo):
     U, P, Q, phi = inputs
     lat = _lat()
     Ud, Pd = _cuda(U), _cuda(P)
-    a = lat.hmc_trajectory(Ud, Pd, BETA, 0.05, 6, phi=_cuda(phi), cg_tol=1e-14)
+    a = lat.hmc_trajectory(Ud, Pd, BETA, 0.05, 6, phi=_cuda(phi), cg_tol=1e-14, eo=eo)
     Pd.neg_()
-    b = lat.hmc_trajectory(Ud, Pd, BETA, 0.05, 6, phi=_cuda(phi), cg_tol=1e-14)
+    b = lat.hmc_trajectory(Ud, Pd, BETA, 0.05, 6, phi=_cuda(phi), cg_tol=1e-14, eo=eo)
     assert np.abs(Ud.cpu().numpy() - U).max() < 1e-10
     assert np.abs(Pd.cpu().numpy() + P).max() < 1e-9
     assert a["dH"] + b["dH"] == pytest.approx(0.0, abs=1e-8)
