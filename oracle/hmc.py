@@ -12,8 +12,10 @@ pseudofermion field:
 
 P is traceless Hermitian per link.  A link moves as U -> exp(i eps P) U and the
 force F(U) is the traceless Hermitian matrix with dS/de = Tr(H F) along
-U -> exp(i e H) U, so that dP/dtau = -F conserves H.  The integrator is leapfrog:
-half step in P, n alternating full steps, half step in P.
+U -> exp(i e H) U, so that dP/dtau = -F conserves H.  Integrators: leapfrog (half
+step in P, n alternating full steps, half step in P) and the second-order
+minimum-norm (Omelyan) scheme, whose coefficient lambda minimises the norm of the
+leading error terms.
 
 Nothing here is shared with the GPU library; the fermion parts call the C oracle
 (CG, M and the fermion force in its Lie-algebra form).
@@ -128,16 +130,40 @@ def hamiltonian_and_force(U, P, beta, phi=None, kappa=0.0, bc=None, tol=1e-12, e
     return kinetic(P) + S, F
 
 
-def trajectory(U, P, beta, eps, nsteps, phi=None, kappa=0.0, bc=None, tol=1e-12, eo=False):
-    """One leapfrog trajectory of nsteps steps of size eps.  Returns (U', P', H0, H1);
-    the inputs are not modified.  eo: the even-odd pseudofermion action."""
+# second-order minimum-norm (Omelyan) coefficient
+OMELYAN_LAMBDA = 0.1931833275037836
+
+
+def trajectory(U, P, beta, eps, nsteps, phi=None, kappa=0.0, bc=None, tol=1e-12, eo=False,
+               integrator="leapfrog"):
+    """One trajectory of nsteps steps of size eps.  Returns (U', P', H0, H1); the inputs
+    are not modified.  eo: the even-odd pseudofermion action.  integrator: "leapfrog"
+    (P eps/2, U eps, P eps/2 per step) or "omelyan" (P lambda eps, U eps/2,
+    P (1 - 2 lambda) eps, U eps/2, P lambda eps per step)."""
     U = U.copy()
     P = P.copy()
+
+    def force():
+        return hamiltonian_and_force(U, P, beta, phi, kappa, bc, tol, eo)[1]
+
+    def move(h):
+        return np.einsum("...ij,...jk->...ik", expi(P, h), U)
+
     H0, F = hamiltonian_and_force(U, P, beta, phi, kappa, bc, tol, eo)
-    P -= 0.5 * eps * F
-    for k in range(nsteps):
-        U = np.einsum("...ij,...jk->...ik", expi(P, eps), U)
-        _, F = hamiltonian_and_force(U, P, beta, phi, kappa, bc, tol, eo)
-        P -= (eps if k < nsteps - 1 else 0.5 * eps) * F
+    if integrator == "leapfrog":
+        P -= 0.5 * eps * F
+        for k in range(nsteps):
+            U = move(eps)
+            P -= (eps if k < nsteps - 1 else 0.5 * eps) * force()
+    elif integrator == "omelyan":
+        lam = OMELYAN_LAMBDA
+        P -= lam * eps * F
+        for k in range(nsteps):
+            U = move(0.5 * eps)
+            P -= (1 - 2 * lam) * eps * force()
+            U = move(0.5 * eps)
+            P -= (lam if k == nsteps - 1 else 2 * lam) * eps * force()
+    else:
+        raise ValueError("integrator must be 'leapfrog' or 'omelyan'")
     H1, _ = hamiltonian_and_force(U, P, beta, phi, kappa, bc, tol, eo)
     return U, P, H0, H1

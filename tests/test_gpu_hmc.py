@@ -90,6 +90,20 @@ def test_trajectory_matches_oracle(inputs, fermions):
     assert (info["cg_iterations"] > 0) == bool(fermions)
 
 
+def test_single_step_trajectory_and_momentum_without_second_force(inputs):
+    """nsteps = 1 (half step, one link step, half step) and P -= eps F1 with F2 absent."""
+    U, P, Q, phi = inputs
+    lat = _lat()
+    U1, P1, H0, H1 = hmc.trajectory(U, P, BETA, 0.1, 1)
+    Ud, Pd = _cuda(U), _cuda(P)
+    info = lat.hmc_trajectory(Ud, Pd, BETA, 0.1, 1)
+    assert np.abs(Ud.cpu().numpy() - U1).max() < 1e-12
+    assert info["dH"] == pytest.approx(H1 - H0, abs=1e-8)
+    Pd = _cuda(P)
+    lat.momentum_update(Pd, _cuda(Q), 0.5)
+    np.testing.assert_allclose(Pd.cpu().numpy(), P - 0.5 * Q, rtol=0, atol=1e-15)
+
+
 @pytest.mark.parametrize("eo", [False, True])
 def test_trajectory_reversible(inputs, eo):
     U, P, Q, phi = inputs

@@ -53,6 +53,24 @@ def test_multishift_matches_oracle(fields, system, csw):
         assert np.all(np.where(oracle.parity_mask(DIMS)[..., None, None], 0, xs) == 0)
 
 
+@pytest.mark.parametrize("shifts", [[0.25], list(np.geomspace(1e-3, 10.0, 16))])
+def test_multishift_single_and_sixteen_shifts(fields, shifts):
+    """One shift (no unshifted member) and the maximum of sixteen."""
+    U, b = fields
+    tol = 1e-10
+    want, n_or = multishift.multishift_cg(U, b, shifts, 0.12, GENERIC, system=1, tol=tol)
+    lat = cola.Lattice(DIMS, 0.12, GENERIC)
+    lat.set_gauge(torch.from_numpy(U).cuda())
+    x, info = lat.cg_multishift(torch.from_numpy(b).cuda(), shifts, system=cola.COLA_SYS_SCHUR,
+                                tol=tol)
+    assert info["status"] == cola.COLA_OK, info
+    assert abs(info["iterations"] - n_or) <= 1
+    xs = x.cpu().numpy()
+    for q in range(len(shifts)):
+        assert rel(xs[q], want[q]) < 1e-7
+        assert info["true_rel_residual"][q] <= 2 * tol
+
+
 def test_multishift_argument_errors(fields):
     U, b = fields
     lat = cola.Lattice(DIMS, 0.12, GENERIC)

@@ -98,10 +98,12 @@ def test_even_odd_fermion_force_matches_finite_difference(field):
     assert an == pytest.approx(fd, rel=1e-6)
 
 
-@pytest.mark.parametrize("fermions", [False, True])
-def test_trajectory_reversible(field, fermions):
+@pytest.mark.parametrize("fermions,integrator", [(False, "leapfrog"), (True, "leapfrog"),
+                                                 (True, "omelyan")])
+def test_trajectory_reversible(field, fermions, integrator):
     U, P, H, phi = field
     kw = dict(phi=phi, kappa=0.12, bc=ANTI, tol=1e-14) if fermions else {}
+    kw["integrator"] = integrator
     U1, P1, H0, H1 = hmc.trajectory(U, P, 5.5, 0.05, 6, **kw)
     U2, P2, H1b, H2 = hmc.trajectory(U1, -P1, 5.5, 0.05, 6, **kw)
     assert np.abs(U2 - U).max() < 1e-10
@@ -120,3 +122,17 @@ def test_trajectory_energy_violation_is_second_order(field, fermions):
     assert dH[0] > 1e-6
     for a, b in zip(dH, dH[1:]):
         assert 3.0 < a / b < 5.0, dH
+
+
+def test_omelyan_second_order_and_more_accurate_than_leapfrog(field):
+    """Omelyan: Delta H also quarters when eps halves, and at the same step size it is
+    well below leapfrog's (its coefficient minimises the leading error)."""
+    U, P, H, phi = field
+    kw = dict(phi=phi, kappa=0.12, bc=ANTI, tol=1e-14)
+    om = []
+    for n in (4, 8):
+        _, _, H0, H1 = hmc.trajectory(U, P, 5.5, 0.4 / n, n, integrator="omelyan", **kw)
+        om.append(abs(H1 - H0))
+    _, _, H0, H1 = hmc.trajectory(U, P, 5.5, 0.1, 4, **kw)
+    assert 3.0 < om[0] / om[1] < 5.0, om
+    assert om[0] < 0.3 * abs(H1 - H0)
