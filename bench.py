@@ -252,6 +252,12 @@ def workloads_mode(args):
         P.copy_(P0)
         torch.cuda.synchronize()
         ieo = lat.hmc_trajectory(U, P, beta, eps, nsteps, phi=phi_e, cg_tol=1e-10, eo=True)
+        # Omelyan with half as many steps (about the same number of force evaluations)
+        U.copy_(U0)
+        P.copy_(P0)
+        torch.cuda.synchronize()
+        iom = lat.hmc_trajectory(U, P, beta, 2 * eps, nsteps // 2, phi=phi_e, cg_tol=1e-10,
+                                 eo=True, integrator="omelyan")
         V = int(np.prod(dims))
         nl = 4 * V
         F = lat.gauge_force(U, beta)
@@ -276,6 +282,10 @@ def workloads_mode(args):
                           "eo": {"trajectory_seconds": ieo["seconds"], "dH": ieo["dH"],
                                  "cg_iterations": ieo["cg_iterations"],
                                  "status": ieo["status"]},
+                          "eo_omelyan_half_steps": {"trajectory_seconds": iom["seconds"],
+                                                    "dH": iom["dH"],
+                                                    "cg_iterations": iom["cg_iterations"],
+                                                    "status": iom["status"]},
                           "gauge_force_ms": gms, "gauge_force_GBs": nl * 288 / gms / 1e6,
                           "link_update_ms": lms, "link_update_GBs": nl * 432 / lms / 1e6}),
               flush=True)

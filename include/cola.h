@@ -255,6 +255,9 @@ typedef struct {
     int eo;          /* 1: even-odd pseudofermion S_f = phi_e^H (S^H S)^{-1} phi_e,
                         S = 1 - kappa^2 D_eo D_oe, phi's odd sites ignored (its solves
                         run on the half lattice); 0: phi^H (M^H M)^{-1} phi            */
+    int integrator;  /* 0: leapfrog (nsteps + 1 force evaluations); 1: second-order
+                        minimum-norm (Omelyan, lambda = 0.1931833275037836; 2 nsteps + 1
+                        force evaluations, a smaller energy violation per step)        */
 } cola_hmc_params_t;
 
 typedef struct {
@@ -266,8 +269,8 @@ typedef struct {
     double seconds;       /* wall time                                                */
 } cola_hmc_result_t;
 
-/* One leapfrog trajectory (half step in P, nsteps alternating link and momentum steps,
- * half step in P) in place on U and P; phi = NULL for the pure gauge theory.  The
+/* One trajectory (leapfrog: half step in P, nsteps alternating link and momentum steps,
+ * half step in P; or Omelyan, see integrator) in place on U and P; phi = NULL for the pure gauge theory.  The
  * accept/reject decision is the caller's (it keeps a copy of U and draws the uniform
  * number).  With phi: needs csw = 0, re-packs the handle's gauge field from U at every
  * step (cola_set_gauge) and leaves it packed from the final U.  Returns COLA_EINVAL for

@@ -195,6 +195,8 @@ int cola_hmc_trajectory(cola_handle_t *h, void *U, void *P, const void *phi,
         return set_error(h, COLA_EINVAL, "fermion force of the clover term not available");
     if (phi && (!(p->cg_tol > 0.0) || p->cg_max_iter < 1))
         return set_error(h, COLA_EINVAL, "need cg_tol > 0 and cg_max_iter >= 1");
+    if (p->integrator != 0 && p->integrator != 1)
+        return set_error(h, COLA_EINVAL, "integrator must be 0 (leapfrog) or 1 (Omelyan)");
     hipStream_t st = hstream(stream);
     const auto t0 = std::chrono::steady_clock::now();
     HmcWork w;
@@ -208,14 +210,35 @@ int cola_hmc_trajectory(cola_handle_t *h, void *U, void *P, const void *phi,
     // H0 and the force at the start
     COLA_TRY(kinetic(h, P, w, st, &r->kinetic0));
     COLA_TRY(forces(h, U, phi, p, w, true, true, &r->gauge0, &r->fermion0, &iters, &status, st));
-    COLA_HIP(h, launch_momentum_update(P, w.Fg, phi ? w.Ff : nullptr, 0.5 * eps, nl, st));
-    for (int k = 0; k < p->nsteps; ++k) {
-        COLA_HIP(h, launch_link_update(U, P, eps, nl, st));
-        const bool last = k == p->nsteps - 1;
-        COLA_TRY(forces(h, U, phi, p, w, false, last, &r->gauge1, &r->fermion1, &iters, &status,
-                        st));
-        COLA_HIP(h, launch_momentum_update(P, w.Fg, phi ? w.Ff : nullptr, last ? 0.5 * eps : eps,
-                                           nl, st));
+    const void *Ff = phi ? w.Ff : nullptr;
+    if (p->integrator == 0) {
+        // leapfrog: P eps/2, then per step U eps and P eps (eps/2 after the last)
+        COLA_HIP(h, launch_momentum_update(P, w.Fg, Ff, 0.5 * eps, nl, st));
+        for (int k = 0; k < p->nsteps; ++k) {
+            COLA_HIP(h, launch_link_update(U, P, eps, nl, st));
+            const bool last = k == p->nsteps - 1;
+            COLA_TRY(forces(h, U, phi, p, w, false, last, &r->gauge1, &r->fermion1, &iters,
+                            &status, st));
+            COLA_HIP(h, launch_momentum_update(P, w.Fg, Ff, last ? 0.5 * eps : eps, nl, st));
+        }
+    } else {
+        // Omelyan: P lambda eps, then per step U eps/2, P (1 - 2 lambda) eps, U eps/2 and
+        // P 2 lambda eps (the next step's first momentum step merged; lambda eps after the
+        // last)
+        const double lam = 0.1931833275037836;
+        COLA_HIP(h, launch_momentum_update(P, w.Fg, Ff, lam * eps, nl, st));
+        for (int k = 0; k < p->nsteps; ++k) {
+            const bool last = k == p->nsteps - 1;
+            COLA_HIP(h, launch_link_update(U, P, 0.5 * eps, nl, st));
+            COLA_TRY(forces(h, U, phi, p, w, false, false, nullptr, nullptr, &iters, &status,
+                            st));
+            COLA_HIP(h, launch_momentum_update(P, w.Fg, Ff, (1.0 - 2.0 * lam) * eps, nl, st));
+            COLA_HIP(h, launch_link_update(U, P, 0.5 * eps, nl, st));
+            COLA_TRY(forces(h, U, phi, p, w, false, last, &r->gauge1, &r->fermion1, &iters,
+                            &status, st));
+            COLA_HIP(h, launch_momentum_update(P, w.Fg, Ff, (last ? lam : 2.0 * lam) * eps, nl,
+                                               st));
+        }
     }
     COLA_TRY(kinetic(h, P, w, st, &r->kinetic1));
     COLA_HIP(h, hipStreamSynchronize(st));

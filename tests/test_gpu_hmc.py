@@ -70,17 +70,19 @@ def test_momentum_update(inputs):
     np.testing.assert_allclose(Pd.cpu().numpy(), P - 0.3 * (F1 + Q), rtol=0, atol=1e-14)
 
 
-@pytest.mark.parametrize("fermions", [False, True, "eo"])
-def test_trajectory_matches_oracle(inputs, fermions):
+@pytest.mark.parametrize("fermions,integrator", [(False, "leapfrog"), (True, "leapfrog"),
+                                                 ("eo", "leapfrog"), (False, "omelyan"),
+                                                 ("eo", "omelyan")])
+def test_trajectory_matches_oracle(inputs, fermions, integrator):
     """fermions: none, the full-lattice pseudofermion, or the even-odd one."""
     U, P, Q, phi = inputs
     lat = _lat()
     eo = fermions == "eo"
     kw = dict(phi=phi, kappa=0.12, bc=ANTI, tol=1e-13, eo=eo) if fermions else {}
-    U1, P1, H0, H1 = hmc.trajectory(U, P, BETA, 0.05, 5, **kw)
+    U1, P1, H0, H1 = hmc.trajectory(U, P, BETA, 0.05, 5, integrator=integrator, **kw)
     Ud, Pd = _cuda(U), _cuda(P)
     info = lat.hmc_trajectory(Ud, Pd, BETA, 0.05, 5, phi=_cuda(phi) if fermions else None,
-                              cg_tol=1e-13, eo=eo)
+                              cg_tol=1e-13, eo=eo, integrator=integrator)
     assert info["status"] == cola.COLA_OK, info
     assert np.abs(Ud.cpu().numpy() - U1).max() < 1e-10
     assert np.abs(Pd.cpu().numpy() - P1).max() < 1e-9
@@ -104,14 +106,17 @@ def test_single_step_trajectory_and_momentum_without_second_force(inputs):
     np.testing.assert_allclose(Pd.cpu().numpy(), P - 0.5 * Q, rtol=0, atol=1e-15)
 
 
-@pytest.mark.parametrize("eo", [False, True])
-def test_trajectory_reversible(inputs, eo):
+@pytest.mark.parametrize("eo,integrator", [(False, "leapfrog"), (True, "leapfrog"),
+                                            (True, "omelyan")])
+def test_trajectory_reversible(inputs, eo, integrator):
     U, P, Q, phi = inputs
     lat = _lat()
     Ud, Pd = _cuda(U), _cuda(P)
-    a = lat.hmc_trajectory(Ud, Pd, BETA, 0.05, 6, phi=_cuda(phi), cg_tol=1e-14, eo=eo)
+    a = lat.hmc_trajectory(Ud, Pd, BETA, 0.05, 6, phi=_cuda(phi), cg_tol=1e-14, eo=eo,
+                           integrator=integrator)
     Pd.neg_()
-    b = lat.hmc_trajectory(Ud, Pd, BETA, 0.05, 6, phi=_cuda(phi), cg_tol=1e-14, eo=eo)
+    b = lat.hmc_trajectory(Ud, Pd, BETA, 0.05, 6, phi=_cuda(phi), cg_tol=1e-14, eo=eo,
+                           integrator=integrator)
     assert np.abs(Ud.cpu().numpy() - U).max() < 1e-10
     assert np.abs(Pd.cpu().numpy() + P).max() < 1e-9
     assert a["dH"] + b["dH"] == pytest.approx(0.0, abs=1e-8)
