@@ -6,7 +6,9 @@
  * Lattice 2022) describes: the Wilson(-clover) Dirac operator applied to a
  * fermion field ("fermion matrix"), conjugate-gradient solves with it in
  * plain FP64 and in mixed precision (32-bit inner iterations, 64-bit outer
- * solver), and the force term of Hybrid Monte Carlo.  The paper's GPU code is
+ * solver), and the force term of Hybrid Monte Carlo; around them, the HMC
+ * molecular-dynamics trajectory (gauge force, link and momentum updates, leapfrog and
+ * Omelyan integrators) and the multi-shift CG of rational HMC.  The paper's GPU code is
  * reached from Fortran through an ISO C binding; this header is the same kind
  * of plain-C boundary: POD types, raw pointers, no C++ or torch types.
  *
@@ -25,8 +27,9 @@
  *   packed    the library's own per-parity structure-of-arrays form in one of the
  *             precisions below (see cola_field_bytes); made by cola_pack_spinor.
  *   streams   `stream` is a hipStream_t (NULL = default stream).  dslash_apply,
- *             pack/unpack and fermion_force are asynchronous on it; set_gauge and
- *             cg_solve synchronise it before returning.
+ *             pack/unpack, the forces and the link/momentum updates are asynchronous on
+ *             it; set_gauge, the solvers, gauge_action and hmc_trajectory synchronise it
+ *             before returning.
  *   ownership the caller owns every buffer passed in; the library owns its packed
  *             gauge/clover copies and its workspace, released by cola_destroy.
  *   errors    0 = COLA_OK; negative = nothing valid was produced (message in
