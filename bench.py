@@ -258,6 +258,13 @@ def workloads_mode(args):
         torch.cuda.synchronize()
         iom = lat.hmc_trajectory(U, P, beta, 2 * eps, nsteps // 2, phi=phi_e, cg_tol=1e-10,
                                  eo=True, integrator="omelyan")
+        # the same with FP32 solves and FP64 reliable updates
+        U.copy_(U0)
+        P.copy_(P0)
+        torch.cuda.synchronize()
+        imx = lat.hmc_trajectory(U, P, beta, 2 * eps, nsteps // 2, phi=phi_e, cg_tol=1e-10,
+                                 eo=True, integrator="omelyan",
+                                 cg_scheme=cola.COLA_CG_FP32_RELIABLE)
         V = int(np.prod(dims))
         nl = 4 * V
         F = lat.gauge_force(U, beta)
@@ -286,6 +293,10 @@ def workloads_mode(args):
                                                     "dH": iom["dH"],
                                                     "cg_iterations": iom["cg_iterations"],
                                                     "status": iom["status"]},
+                          "eo_omelyan_fp32_reliable": {"trajectory_seconds": imx["seconds"],
+                                                       "dH": imx["dH"],
+                                                       "cg_iterations": imx["cg_iterations"],
+                                                       "status": imx["status"]},
                           "gauge_force_ms": gms, "gauge_force_GBs": nl * 288 / gms / 1e6,
                           "link_update_ms": lms, "link_update_GBs": nl * 432 / lms / 1e6}),
               flush=True)

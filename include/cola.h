@@ -261,6 +261,8 @@ typedef struct {
     int integrator;  /* 0: leapfrog (nsteps + 1 force evaluations); 1: second-order
                         minimum-norm (Omelyan, lambda = 0.1931833275037836; 2 nsteps + 1
                         force evaluations, a smaller energy violation per step)        */
+    int cg_scheme;   /* COLA_CG_* of the fermion solves (0 = FP64); the mixed schemes
+                        still reach cg_tol in FP64 true residual                        */
 } cola_hmc_params_t;
 
 typedef struct {

@@ -55,7 +55,7 @@ class CgResult(ctypes.Structure):
 class HmcParams(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("eps", ctypes.c_double), ("nsteps", ctypes.c_int),
                 ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int), ("eo", ctypes.c_int),
-                ("integrator", ctypes.c_int)]
+                ("integrator", ctypes.c_int), ("cg_scheme", ctypes.c_int)]
 
 
 class HmcResult(ctypes.Structure):
@@ -409,7 +409,7 @@ class Lattice:
 
     def hmc_trajectory(self, U: torch.Tensor, P: torch.Tensor, beta: float, eps: float,
                        nsteps: int, phi=None, cg_tol=1e-12, cg_max_iter=20000, eo=False,
-                       integrator="leapfrog") -> dict:
+                       integrator="leapfrog", cg_scheme=COLA_CG_FP64) -> dict:
         """One trajectory in place on U and P (phi: pseudofermion or None; eo: the even-odd
         pseudofermion action; integrator: "leapfrog" or "omelyan")."""
         if integrator not in ("leapfrog", "omelyan"):
@@ -421,7 +421,7 @@ class Lattice:
                 raise ValueError("phi must be one canonical spinor")
             phi = phi.contiguous()
         prm = HmcParams(float(beta), float(eps), int(nsteps), float(cg_tol), int(cg_max_iter),
-                        1 if eo else 0, 1 if integrator == "omelyan" else 0)
+                        1 if eo else 0, 1 if integrator == "omelyan" else 0, int(cg_scheme))
         r = HmcResult()
         cola_hmc_trajectory(self.h, _ptr(U), _ptr(P), _ptr(phi) if phi is not None else None,
                             prm, r, _stream())

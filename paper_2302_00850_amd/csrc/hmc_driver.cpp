@@ -61,7 +61,7 @@ int forces_eo(cola_handle_t *h, const void *phi, const cola_hmc_params_t *p, Hmc
               bool first, bool energy, double *sf, int *iters, int *status, hipStream_t st) {
     cola_cg_params_t cp{};
     cp.system = COLA_SYS_SCHUR;
-    cp.scheme = COLA_CG_FP64;
+    cp.scheme = p->cg_scheme;
     cp.tol = p->cg_tol;
     cp.max_iter = p->cg_max_iter;
     cp.reliable_interval = 50;
@@ -114,7 +114,7 @@ int forces(cola_handle_t *h, void *U, const void *phi, const cola_hmc_params_t *
     if (p->eo) return forces_eo(h, phi, p, w, first, energy, sf, iters, status, st);
     cola_cg_params_t cp{};
     cp.system = COLA_SYS_MDAGM;
-    cp.scheme = COLA_CG_FP64;
+    cp.scheme = p->cg_scheme;
     cp.tol = p->cg_tol;
     cp.max_iter = p->cg_max_iter;
     cp.reliable_interval = 50;
@@ -195,6 +195,8 @@ int cola_hmc_trajectory(cola_handle_t *h, void *U, void *P, const void *phi,
         return set_error(h, COLA_EINVAL, "fermion force of the clover term not available");
     if (phi && (!(p->cg_tol > 0.0) || p->cg_max_iter < 1))
         return set_error(h, COLA_EINVAL, "need cg_tol > 0 and cg_max_iter >= 1");
+    if (phi && (p->cg_scheme < COLA_CG_FP64 || p->cg_scheme > COLA_CG_FP32_DEFECT))
+        return set_error(h, COLA_EINVAL, "unknown cg_scheme");
     if (p->integrator != 0 && p->integrator != 1)
         return set_error(h, COLA_EINVAL, "integrator must be 0 (leapfrog) or 1 (Omelyan)");
     hipStream_t st = hstream(stream);

@@ -92,6 +92,24 @@ def test_trajectory_matches_oracle(inputs, fermions, integrator):
     assert (info["cg_iterations"] > 0) == bool(fermions)
 
 
+@pytest.mark.parametrize("scheme", ["FP32_RELIABLE", "FP16_DEFECT"])
+def test_trajectory_mixed_precision_solves(inputs, scheme):
+    """The fermion solves in mixed precision (FP64 true residual to cg_tol) give the
+    FP64 oracle's trajectory to the solver tolerance."""
+    U, P, Q, phi = inputs
+    lat = _lat()
+    U1, P1, H0, H1 = hmc.trajectory(U, P, BETA, 0.05, 4, phi=phi, kappa=0.12, bc=ANTI,
+                                    tol=1e-13, eo=True, integrator="omelyan")
+    Ud, Pd = _cuda(U), _cuda(P)
+    info = lat.hmc_trajectory(Ud, Pd, BETA, 0.05, 4, phi=_cuda(phi), cg_tol=1e-12, eo=True,
+                              integrator="omelyan",
+                              cg_scheme=getattr(cola, "COLA_CG_" + scheme))
+    assert info["status"] == cola.COLA_OK, info
+    assert np.abs(Ud.cpu().numpy() - U1).max() < 1e-9
+    assert np.abs(Pd.cpu().numpy() - P1).max() < 1e-8
+    assert info["dH"] == pytest.approx(H1 - H0, abs=1e-6)
+
+
 def test_single_step_trajectory_and_momentum_without_second_force(inputs):
     """nsteps = 1 (half step, one link step, half step) and P -= eps F1 with F2 absent."""
     U, P, Q, phi = inputs
