@@ -265,6 +265,13 @@ def workloads_mode(args):
         imx = lat.hmc_trajectory(U, P, beta, 2 * eps, nsteps // 2, phi=phi_e, cg_tol=1e-10,
                                  eo=True, integrator="omelyan",
                                  cg_scheme=cola.COLA_CG_FP32_RELIABLE)
+        # two time scales: 5 fermion steps of 2 eps, 4 gauge sub-steps each
+        U.copy_(U0)
+        P.copy_(P0)
+        torch.cuda.synchronize()
+        its = lat.hmc_trajectory(U, P, beta, 2 * eps, nsteps // 2, phi=phi_e, cg_tol=1e-10,
+                                 eo=True, integrator="leapfrog_mts", n_gauge=4,
+                                 cg_scheme=cola.COLA_CG_FP32_RELIABLE)
         V = int(np.prod(dims))
         nl = 4 * V
         F = lat.gauge_force(U, beta)
@@ -297,6 +304,10 @@ def workloads_mode(args):
                                                        "dH": imx["dH"],
                                                        "cg_iterations": imx["cg_iterations"],
                                                        "status": imx["status"]},
+                          "eo_two_scales_fp32_reliable": {"trajectory_seconds": its["seconds"],
+                                                          "dH": its["dH"],
+                                                          "cg_iterations": its["cg_iterations"],
+                                                          "n_gauge": 4, "status": its["status"]},
                           "gauge_force_ms": gms, "gauge_force_GBs": nl * 288 / gms / 1e6,
                           "link_update_ms": lms, "link_update_GBs": nl * 432 / lms / 1e6}),
               flush=True)

@@ -260,7 +260,10 @@ typedef struct {
                         run on the half lattice); 0: phi^H (M^H M)^{-1} phi            */
     int integrator;  /* 0: leapfrog (nsteps + 1 force evaluations); 1: second-order
                         minimum-norm (Omelyan, lambda = 0.1931833275037836; 2 nsteps + 1
-                        force evaluations, a smaller energy violation per step)        */
+                        force evaluations, a smaller energy violation per step);
+                        2: leapfrog on two time scales, the fermion force on steps of
+                        eps and the gauge force on n_gauge sub-steps of eps / n_gauge  */
+    int n_gauge;     /* gauge sub-steps per step for integrator 2 (>= 1)               */
     int cg_scheme;   /* COLA_CG_* of the fermion solves (0 = FP64); the mixed schemes
                         still reach cg_tol in FP64 true residual                        */
 } cola_hmc_params_t;

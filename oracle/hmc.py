@@ -135,16 +135,22 @@ OMELYAN_LAMBDA = 0.1931833275037836
 
 
 def trajectory(U, P, beta, eps, nsteps, phi=None, kappa=0.0, bc=None, tol=1e-12, eo=False,
-               integrator="leapfrog"):
+               integrator="leapfrog", n_gauge=1):
     """One trajectory of nsteps steps of size eps.  Returns (U', P', H0, H1); the inputs
     are not modified.  eo: the even-odd pseudofermion action.  integrator: "leapfrog"
-    (P eps/2, U eps, P eps/2 per step) or "omelyan" (P lambda eps, U eps/2,
-    P (1 - 2 lambda) eps, U eps/2, P lambda eps per step)."""
+    (P eps/2, U eps, P eps/2 per step), "omelyan" (P lambda eps, U eps/2,
+    P (1 - 2 lambda) eps, U eps/2, P lambda eps per step) or "leapfrog_mts" (fermion
+    kicks of eps around n_gauge gauge-force leapfrog sub-steps)."""
     U = U.copy()
     P = P.copy()
 
     def force():
         return hamiltonian_and_force(U, P, beta, phi, kappa, bc, tol, eo)[1]
+
+    def fermion_force():
+        if phi is None:
+            return np.zeros_like(U)
+        return (_fermion_eo if eo else _fermion)(U, phi, kappa, bc, tol)[1]
 
     def move(h):
         return np.einsum("...ij,...jk->...ik", expi(P, h), U)
@@ -155,6 +161,17 @@ def trajectory(U, P, beta, eps, nsteps, phi=None, kappa=0.0, bc=None, tol=1e-12,
         for k in range(nsteps):
             U = move(eps)
             P -= (eps if k < nsteps - 1 else 0.5 * eps) * force()
+    elif integrator == "leapfrog_mts":
+        # two time scales (Sexton-Weingarten): the fermion force on steps of eps, the gauge
+        # force on n_gauge leapfrog sub-steps of eps / n_gauge between the fermion kicks
+        h = eps / n_gauge
+        P -= 0.5 * eps * fermion_force()
+        for k in range(nsteps):
+            P -= 0.5 * h * gauge_force(U, beta)
+            for j in range(n_gauge):
+                U = move(h)
+                P -= (h if j < n_gauge - 1 else 0.5 * h) * gauge_force(U, beta)
+            P -= (eps if k < nsteps - 1 else 0.5 * eps) * fermion_force()
     elif integrator == "omelyan":
         lam = OMELYAN_LAMBDA
         P -= lam * eps * F

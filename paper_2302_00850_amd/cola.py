@@ -55,7 +55,8 @@ class CgResult(ctypes.Structure):
 class HmcParams(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("eps", ctypes.c_double), ("nsteps", ctypes.c_int),
                 ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int), ("eo", ctypes.c_int),
-                ("integrator", ctypes.c_int), ("cg_scheme", ctypes.c_int)]
+                ("integrator", ctypes.c_int), ("n_gauge", ctypes.c_int),
+                ("cg_scheme", ctypes.c_int)]
 
 
 class HmcResult(ctypes.Structure):
@@ -409,11 +410,13 @@ class Lattice:
 
     def hmc_trajectory(self, U: torch.Tensor, P: torch.Tensor, beta: float, eps: float,
                        nsteps: int, phi=None, cg_tol=1e-12, cg_max_iter=20000, eo=False,
-                       integrator="leapfrog", cg_scheme=COLA_CG_FP64) -> dict:
+                       integrator="leapfrog", cg_scheme=COLA_CG_FP64, n_gauge=1) -> dict:
         """One trajectory in place on U and P (phi: pseudofermion or None; eo: the even-odd
-        pseudofermion action; integrator: "leapfrog" or "omelyan")."""
-        if integrator not in ("leapfrog", "omelyan"):
-            raise ValueError("integrator must be 'leapfrog' or 'omelyan'")
+        pseudofermion action; integrator: "leapfrog", "omelyan" or "leapfrog_mts" with
+        n_gauge gauge sub-steps per fermion step)."""
+        kinds = {"leapfrog": 0, "omelyan": 1, "leapfrog_mts": 2}
+        if integrator not in kinds:
+            raise ValueError(f"integrator must be one of {sorted(kinds)}")
         self._gauge_like(U, "U")
         self._gauge_like(P, "P")
         if phi is not None:
@@ -421,7 +424,7 @@ class Lattice:
                 raise ValueError("phi must be one canonical spinor")
             phi = phi.contiguous()
         prm = HmcParams(float(beta), float(eps), int(nsteps), float(cg_tol), int(cg_max_iter),
-                        1 if eo else 0, 1 if integrator == "omelyan" else 0, int(cg_scheme))
+                        1 if eo else 0, kinds[integrator], int(n_gauge), int(cg_scheme))
         r = HmcResult()
         cola_hmc_trajectory(self.h, _ptr(U), _ptr(P), _ptr(phi) if phi is not None else None,
                             prm, r, _stream())

@@ -27,12 +27,17 @@ struct HmcWork {
     double *sc = nullptr;               // 4 device scalars
 };
 
+int scalars(cola_handle_t *h, double **sc) {
+    void *p;
+    COLA_TRY(get_vec(h, "hmc_sc", 4 * sizeof(double), &p));
+    *sc = (double *)p;
+    return COLA_OK;
+}
+
 int work(cola_handle_t *h, bool fermions, HmcWork *w) {
     const size_t gb = nlinks(h) * 9 * 16;
     COLA_TRY(get_vec(h, "hmc_Fg", gb, &w->Fg));
-    void *sc;
-    COLA_TRY(get_vec(h, "hmc_sc", 4 * sizeof(double), &sc));
-    w->sc = (double *)sc;
+    COLA_TRY(scalars(h, &w->sc));
     if (!fermions) return COLA_OK;
     const size_t sb = (size_t)2 * h->g.Vh * 12 * 16;
     const size_t pb = cola_field_bytes(h, COLA_FP64, 1, -1);
@@ -158,12 +163,12 @@ int cola_gauge_force(cola_handle_t *h, void *F, const void *U, double beta, void
 int cola_gauge_action(cola_handle_t *h, const void *U, double beta, double *S, void *stream) {
     if (!h) return COLA_EINVAL;
     if (!U || !S) return set_error(h, COLA_EINVAL, "null pointer");
-    HmcWork w;
-    COLA_TRY(work(h, false, &w));
+    double *sc;
+    COLA_TRY(scalars(h, &sc));
     hipStream_t st = hstream(stream);
-    COLA_HIP(h, launch_plaquette_sum(h->g, U, h->partial, w.sc, st));
+    COLA_HIP(h, launch_plaquette_sum(h->g, U, h->partial, sc, st));
     int rc = COLA_OK;
-    const double plaq = read_scalar(h, w.sc, st, &rc);
+    const double plaq = read_scalar(h, sc, st, &rc);
     COLA_TRY(rc);
     *S = beta * (6.0 * 2.0 * h->g.Vh - plaq / 3.0);
     return COLA_OK;
@@ -197,8 +202,11 @@ int cola_hmc_trajectory(cola_handle_t *h, void *U, void *P, const void *phi,
         return set_error(h, COLA_EINVAL, "need cg_tol > 0 and cg_max_iter >= 1");
     if (phi && (p->cg_scheme < COLA_CG_FP64 || p->cg_scheme > COLA_CG_FP32_DEFECT))
         return set_error(h, COLA_EINVAL, "unknown cg_scheme");
-    if (p->integrator != 0 && p->integrator != 1)
-        return set_error(h, COLA_EINVAL, "integrator must be 0 (leapfrog) or 1 (Omelyan)");
+    if (p->integrator < 0 || p->integrator > 2)
+        return set_error(h, COLA_EINVAL,
+                         "integrator must be 0 (leapfrog), 1 (Omelyan) or 2 (two time scales)");
+    if (p->integrator == 2 && p->n_gauge < 1)
+        return set_error(h, COLA_EINVAL, "n_gauge must be >= 1");
     hipStream_t st = hstream(stream);
     const auto t0 = std::chrono::steady_clock::now();
     HmcWork w;
@@ -222,6 +230,28 @@ int cola_hmc_trajectory(cola_handle_t *h, void *U, void *P, const void *phi,
             COLA_TRY(forces(h, U, phi, p, w, false, last, &r->gauge1, &r->fermion1, &iters,
                             &status, st));
             COLA_HIP(h, launch_momentum_update(P, w.Fg, Ff, last ? 0.5 * eps : eps, nl, st));
+        }
+    } else if (p->integrator == 2) {
+        // two time scales: fermion kicks of eps around n_gauge gauge leapfrog sub-steps of
+        // eps / n_gauge (w.Fg and w.Ff hold the forces at the current U)
+        const int m = p->n_gauge;
+        const double hs = eps / m;
+        if (Ff) COLA_HIP(h, launch_momentum_update(P, Ff, nullptr, 0.5 * eps, nl, st));
+        for (int k = 0; k < p->nsteps; ++k) {
+            const bool last = k == p->nsteps - 1;
+            COLA_HIP(h, launch_momentum_update(P, w.Fg, nullptr, 0.5 * hs, nl, st));
+            for (int j = 0; j < m; ++j) {
+                COLA_HIP(h, launch_link_update(U, P, hs, nl, st));
+                COLA_HIP(h, launch_gauge_force(h->g, U, w.Fg, p->beta, st));
+                COLA_HIP(h, launch_momentum_update(P, w.Fg, nullptr, j < m - 1 ? hs : 0.5 * hs,
+                                                   nl, st));
+            }
+            // the fermion force (and, after the last step, the energies) at the new U
+            COLA_TRY(forces(h, U, phi, p, w, false, last, &r->gauge1, &r->fermion1, &iters,
+                            &status, st));
+            if (Ff)
+                COLA_HIP(h, launch_momentum_update(P, Ff, nullptr, last ? 0.5 * eps : eps, nl,
+                                                   st));
         }
     } else {
         // Omelyan: P lambda eps, then per step U eps/2, P (1 - 2 lambda) eps, U eps/2 and

@@ -72,17 +72,19 @@ def test_momentum_update(inputs):
 
 @pytest.mark.parametrize("fermions,integrator", [(False, "leapfrog"), (True, "leapfrog"),
                                                  ("eo", "leapfrog"), (False, "omelyan"),
-                                                 ("eo", "omelyan")])
+                                                 ("eo", "omelyan"), ("eo", "leapfrog_mts"),
+                                                 (False, "leapfrog_mts")])
 def test_trajectory_matches_oracle(inputs, fermions, integrator):
     """fermions: none, the full-lattice pseudofermion, or the even-odd one."""
     U, P, Q, phi = inputs
     lat = _lat()
     eo = fermions == "eo"
     kw = dict(phi=phi, kappa=0.12, bc=ANTI, tol=1e-13, eo=eo) if fermions else {}
-    U1, P1, H0, H1 = hmc.trajectory(U, P, BETA, 0.05, 5, integrator=integrator, **kw)
+    U1, P1, H0, H1 = hmc.trajectory(U, P, BETA, 0.05, 5, integrator=integrator, n_gauge=3,
+                                    **kw)
     Ud, Pd = _cuda(U), _cuda(P)
     info = lat.hmc_trajectory(Ud, Pd, BETA, 0.05, 5, phi=_cuda(phi) if fermions else None,
-                              cg_tol=1e-13, eo=eo, integrator=integrator)
+                              cg_tol=1e-13, eo=eo, integrator=integrator, n_gauge=3)
     assert info["status"] == cola.COLA_OK, info
     assert np.abs(Ud.cpu().numpy() - U1).max() < 1e-10
     assert np.abs(Pd.cpu().numpy() - P1).max() < 1e-9
@@ -125,16 +127,16 @@ def test_single_step_trajectory_and_momentum_without_second_force(inputs):
 
 
 @pytest.mark.parametrize("eo,integrator", [(False, "leapfrog"), (True, "leapfrog"),
-                                            (True, "omelyan")])
+                                            (True, "omelyan"), (True, "leapfrog_mts")])
 def test_trajectory_reversible(inputs, eo, integrator):
     U, P, Q, phi = inputs
     lat = _lat()
     Ud, Pd = _cuda(U), _cuda(P)
     a = lat.hmc_trajectory(Ud, Pd, BETA, 0.05, 6, phi=_cuda(phi), cg_tol=1e-14, eo=eo,
-                           integrator=integrator)
+                           integrator=integrator, n_gauge=3)
     Pd.neg_()
     b = lat.hmc_trajectory(Ud, Pd, BETA, 0.05, 6, phi=_cuda(phi), cg_tol=1e-14, eo=eo,
-                           integrator=integrator)
+                           integrator=integrator, n_gauge=3)
     assert np.abs(Ud.cpu().numpy() - U).max() < 1e-10
     assert np.abs(Pd.cpu().numpy() + P).max() < 1e-9
     assert a["dH"] + b["dH"] == pytest.approx(0.0, abs=1e-8)
@@ -147,6 +149,9 @@ def test_trajectory_argument_errors(inputs):
         lat.hmc_trajectory(_cuda(U), _cuda(P), BETA, 0.05, 0)
     with pytest.raises(cola.ColaError):
         lat.hmc_trajectory(_cuda(U), _cuda(P), BETA, -0.1, 3)
+    with pytest.raises(cola.ColaError):
+        lat.hmc_trajectory(_cuda(U), _cuda(P), BETA, 0.05, 3, integrator="leapfrog_mts",
+                           n_gauge=0)
     clover = _lat(kappa=0.118, csw=1.0)
     with pytest.raises(cola.ColaError):
         clover.hmc_trajectory(_cuda(U), _cuda(P), BETA, 0.05, 3, phi=_cuda(phi))
