@@ -312,6 +312,44 @@ def workloads_mode(args):
                           "link_update_ms": lms, "link_update_GBs": nl * 432 / lms / 1e6}),
               flush=True)
         lat.close()
+    if "quenched" in sel:
+        # pure-gauge HMC from a cold start: the first ntherm trajectories are always kept
+        # (far from equilibrium they violate energy by a lot), then Metropolis; acceptance
+        # and the mean plaquette afterwards (an end-to-end check of the sampler)
+        from paper_2302_00850_amd.synth import unit_gauge
+        dims = (8, 8, 8, 8)
+        beta, eps, nsteps, ntraj, ntherm = 6.0, 0.05, 20, 400, 100
+        s = Synth(7, device="cuda", rng="torch")
+        rng = np.random.default_rng(7)  # the Metropolis draws
+        lat = cola.Lattice(dims, KAPPA, bc, 0.0)
+        U = unit_gauge(dims, device="cuda")
+        V = int(np.prod(dims))
+        acc, plaq, dHs = 0, [], []
+        t0 = time.perf_counter()
+        for k in range(ntraj):
+            P = s.momenta(dims)
+            U0 = U.clone()
+            info = lat.hmc_trajectory(U, P, beta, eps, nsteps, integrator="omelyan")
+            if k < ntherm or rng.random() < np.exp(min(0.0, -info["dH"])):
+                acc += k >= ntherm
+            else:
+                U.copy_(U0)
+            if k >= ntherm:
+                dHs.append(info["dH"])
+                plaq.append(1.0 - lat.gauge_action(U, beta) / (beta * 6 * V))
+        sec = time.perf_counter() - t0
+        n = ntraj - ntherm
+        pl = np.array(plaq)
+        # error of the mean from blocks of 20 trajectories (autocorrelation)
+        blocks = pl[: n - n % 20].reshape(-1, 20).mean(1)
+        print(json.dumps({"workload": "hmc_quenched_8x8x8x8", "lattice": list(dims),
+                          "beta": beta, "eps": eps, "nsteps": nsteps, "integrator": "omelyan",
+                          "trajectories": ntraj, "thermalisation": ntherm,
+                          "acceptance": acc / n, "mean_exp_minus_dH": float(np.mean(np.exp(-np.array(dHs)))),
+                          "plaquette": float(pl.mean()),
+                          "plaquette_err": float(blocks.std(ddof=1) / np.sqrt(len(blocks))),
+                          "seconds": sec}), flush=True)
+        lat.close()
     if "multishift" in sel:
         # 12 shifts of the even-odd normal system (a rational-approximation-like spread)
         # against one unshifted FP64 CG on the benchmark lattice
@@ -393,8 +431,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--mode", default="solve", choices=["solve", "hop", "copy", "workloads"])
-    ap.add_argument("--workloads", default="mixed,force,clover,hmc,multishift",
-                    help="workloads mode: any of mixed, force, clover, hmc, multishift")
+    ap.add_argument("--workloads", default="mixed,force,clover,hmc,multishift,quenched",
+                    help="workloads mode: any of mixed, force, clover, hmc, multishift, "
+                         "quenched")
     ap.add_argument("--block", type=int, default=0, help="use block CG in the multi-RHS solves")
     ap.add_argument("--lattice", default="32,32,32,64", help="hop mode: Lx,Ly,Lz,Lt")
     ap.add_argument("--prec", default="0,2,3", help="hop mode: precisions (0 FP64 .. 3 FP16)")
