@@ -155,3 +155,30 @@ def test_trajectory_argument_errors(inputs):
     clover = _lat(kappa=0.118, csw=1.0)
     with pytest.raises(cola.ColaError):
         clover.hmc_trajectory(_cuda(U), _cuda(P), BETA, 0.05, 3, phi=_cuda(phi))
+
+
+def test_quenched_sampler_reaches_the_known_plaquette():
+    """End to end: pure-gauge HMC (Omelyan, Metropolis with seeded draws) on 4^4 at
+    beta = 6.0 from a cold start; <exp(-dH)> = 1 within errors and the plaquette in the
+    range of this action's known value there (about 0.594 in large volume; 4^4 sits a
+    little above it)."""
+    from paper_2302_00850_amd.synth import unit_gauge
+    dims = (4, 4, 4, 4)
+    beta = 6.0
+    s = Synth(21, device="cuda", rng="torch")
+    rng = np.random.default_rng(21)
+    lat = cola.Lattice(dims, 0.12, ANTI, 0.0)
+    U = unit_gauge(dims, device="cuda")
+    V = int(np.prod(dims))
+    plaq, w = [], []
+    for k in range(300):
+        P = s.momenta(dims)
+        U0 = U.clone()
+        info = lat.hmc_trajectory(U, P, beta, 0.05, 20, integrator="omelyan")
+        if not (k < 50 or rng.random() < np.exp(min(0.0, -info["dH"]))):
+            U.copy_(U0)
+        if k >= 100:
+            w.append(np.exp(-info["dH"]))
+            plaq.append(1.0 - lat.gauge_action(U, beta) / (beta * 6 * V))
+    assert abs(np.mean(w) - 1.0) < 0.05
+    assert 0.58 < np.mean(plaq) < 0.63
