@@ -807,10 +807,12 @@ int cg_multishift_impl(cola_handle_t *h, void *x, const void *b, int nshift, con
                                  SpinorFmt::F64, xb, p64, r64, ap, c.slot(RHO), c.slot(PI),
                                  full ? c.slot(PI2) : nullptr, h->active,
                                  reduce_into(h, RHO_NEW), st));
-        double pi = 0.0, pi2 = 0.0, rho_new = 0.0;
-        COLA_TRY(read_slot(c, PI, &pi));
-        if (full) COLA_TRY(read_slot(c, PI2, &pi2));
-        COLA_TRY(read_slot(c, RHO_NEW, &rho_new));
+        // RHO_NEW, PI and PI2 are consecutive slots: one read-back per iteration
+        static_assert(PI == RHO_NEW + 1 && PI2 == RHO_NEW + 2, "slot order");
+        double sl[3 * kMaxRhs];
+        COLA_HIP(h, hipMemcpyAsync(sl, c.slot(RHO_NEW), sizeof sl, hipMemcpyDeviceToHost, st));
+        COLA_HIP(h, hipStreamSynchronize(st));
+        const double rho_new = sl[0], pi = sl[kMaxRhs], pi2 = full ? sl[2 * kMaxRhs] : 0.0;
         const double alpha = rho / (pi + pi2), beta = rho_new / rho;
         if (!std::isfinite(alpha) || !std::isfinite(beta) || !(pi + pi2 > 0.0)) {
             status = COLA_BREAKDOWN;
