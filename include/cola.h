@@ -252,7 +252,7 @@ int cola_momentum_update(cola_handle_t *h, void *P_dev, const void *F1_dev, cons
 typedef struct {
     double beta;     /* gauge coupling                                              */
     double eps;      /* molecular-dynamics step size                                */
-    int nsteps;      /* leapfrog steps (trajectory length eps * nsteps)             */
+    int nsteps;      /* integrator steps (trajectory length eps * nsteps)           */
     double cg_tol;   /* FP64 CG tolerance of the fermion solves (phi given)        */
     int cg_max_iter; /* cap per solve                                               */
     int eo;          /* 1: even-odd pseudofermion S_f = phi_e^H (S^H S)^{-1} phi_e,
@@ -273,16 +273,18 @@ typedef struct {
     double H0, H1;        /* Hamiltonian before and after                             */
     double dH;            /* H1 - H0 (Metropolis: accept with probability min(1, e^-dH)) */
     double kinetic0, kinetic1, gauge0, gauge1, fermion0, fermion1; /* parts of H0, H1   */
-    int cg_iterations;    /* summed over the nsteps + 1 fermion solves                */
+    int cg_iterations;    /* summed over all fermion solves of the trajectory         */
     double seconds;       /* wall time                                                */
 } cola_hmc_result_t;
 
-/* One trajectory (leapfrog: half step in P, nsteps alternating link and momentum steps,
- * half step in P; or Omelyan, see integrator) in place on U and P; phi = NULL for the pure gauge theory.  The
- * accept/reject decision is the caller's (it keeps a copy of U and draws the uniform
- * number).  With phi: needs csw = 0, re-packs the handle's gauge field from U at every
- * step (cola_set_gauge) and leaves it packed from the final U.  Returns COLA_EINVAL for
- * nsteps < 1, eps <= 0 or non-finite parameters.  Synchronises `stream`. */
+/* One trajectory in place on U and P (leapfrog: half step in P, nsteps alternating link
+ * and momentum steps, half step in P; or the other integrators above); phi = NULL for
+ * the pure gauge theory.  The accept/reject decision is the caller's (it keeps a copy of
+ * U and draws the uniform number).  With phi: needs csw = 0, re-packs the handle's gauge
+ * field from U before every fermion solve (cola_set_gauge) and leaves it packed from
+ * the final U.  Returns COLA_EINVAL for nsteps < 1, eps <= 0, non-finite parameters, an
+ * unknown integrator or cg_scheme, or n_gauge < 1 with integrator 2.  Synchronises
+ * `stream`. */
 int cola_hmc_trajectory(cola_handle_t *h, void *U_dev, void *P_dev, const void *phi_dev,
                         const cola_hmc_params_t *p, cola_hmc_result_t *r, void *stream);
 
