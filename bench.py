@@ -1,17 +1,18 @@
 """Benchmark of the Wilson-Dirac hot path on one MI355X.
 
-Workload (the lattice of the paper's CG benchmark is unspecified; this is the
-multi-RHS mixed-precision case): 32^3 x 64 lattice, plain Wilson, kappa = 0.12,
-periodic space / antiperiodic time, synthetic SU(3) links (seed 0), the 12
-spin-colour point sources at the origin.  One step = one solve of
-S^H S x_e = b_e for all 12 sources to a 1e-10 FP64 true relative residual,
-with FP16-storage CG (FP32 arithmetic, 12-RHS batched hop) inside FP64 defect
-correction.  Reported value: effective GB/s of the FP16 12-RHS hop kernel
-(algorithmic bytes / HIP-event kernel time over the timed steps, over its four
-launches per CG iteration: two plain hops, one with the x - kappa^2 D in epilogue
-and |out|^2, one with the CG update of x and r fused in); also the
-time per source against plain FP64 CG (one source, 18-real links) and the
-FP64 CPU oracle on the machine's host cores.
+Workload (the paper's CG benchmark names no lattice; this is the largest synthetic
+configuration, at the paper's 32-bit inner / 64-bit outer arithmetic): 48^3 x 96
+lattice (10.6M sites), clover-improved Wilson (c_sw = 1, kappa = 0.118), periodic
+space / antiperiodic time, synthetic SU(3) links (seed 0), the 12 spin-colour point
+sources at the origin.  One step = one solve of S^H S x_e = b_e (S the even-odd
+clover Schur complement) for all 12 sources to a 1e-10 FP64 true relative residual,
+FP32 CG (FP32 storage and arithmetic, 12-RHS batched hop) inside FP64 defect
+correction.  Reported value: effective GB/s of the FP32 12-RHS clover hop
+(t_o = A_oo^-1 D_oe p: 2688 B per site for links and spinors plus 288 B of clover
+block, algorithmic bytes / HIP-event kernel time over the timed steps); also the
+time per source against plain FP64 CG (one source, 18-real links), the blended
+GB/s of every FP32 hop launch of the solve, the 32^3 x 64 FP16-storage workload,
+and the FP64 CPU oracle's hop on the same lattice on the machine's host cores.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -32,15 +33,19 @@ sys.path.insert(0, ROOT)
 METRIC = "Dslash GB/s (% HBM peak); CG time-to-1e-10 residual, mixed/multi-RHS vs FP64"
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFS = 78.6  # 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz
-DIMS = (32, 32, 32, 64)
+DIMS = (48, 48, 48, 96)       # the benchmark workload (clover, FP32 inner / FP64 outer)
+KAPPA_C = 0.118
+CSW = 1.0
+DIMS3 = (32, 32, 32, 64)      # the FP16-storage workload, reported beside it
 KAPPA = 0.12
 TOL = 1e-10
+WORKLOAD = "clover_eo_48x48x48x96_12rhs_fp32defect"
 
 
-# rocprofv3 counter summary of the FP16 hop launches of this workload (HBM bytes per
-# launch); valid only for the hop sources it was taken with.
-COUNTERS = os.path.join(ROOT, "profiles", "hop_fp16_12rhs_32x32x32x64_solve_counters.txt")
-HOP_SOURCES = ["hop_impl.h", "device.h", "common.h", "hop_f16_12.hip", "ops.cpp"]
+# rocprofv3 counter summary of the FP32 12-rhs clover hop launches of this workload (HBM
+# bytes per launch); valid only for the hop sources it was taken with.
+COUNTERS = os.path.join(ROOT, "profiles", "hop_fp32_12rhs_clover_48x48x48x96_solve_counters.txt")
+HOP_SOURCES = ["hop_impl.h", "device.h", "common.h", "hop_f32_12.hip", "ops.cpp"]
 
 
 def hop_sources_sha256():
@@ -52,7 +57,7 @@ def hop_sources_sha256():
 
 
 def measured_traffic():
-    """HBM bytes per FP16 hop launch (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    """HBM bytes per FP32 clover hop launch (FETCH_SIZE and WRITE_SIZE, each scaled by the
     same counter's reading for a plain copy of known size) from the committed
     summary, or None when there is none or the hop sources changed since."""
     try:
@@ -73,17 +78,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(U, b, budget_s=12.0):
-    """The FP64 oracle's full-lattice hop on the same lattice, timed on host cores."""
+def cpu_baseline(U, psi, dims, budget_s=15.0):
+    """The FP64 oracle's full-lattice hop D psi on the benchmark lattice, timed on host
+    cores (a bounded sample of hops)."""
     import oracle
 
     from paper_2302_00850_amd.synth import bc_phases
     bc = bc_phases((0, 0, 0, np.pi))
-    V = int(np.prod(DIMS))
-    oracle.hop(U, b, bc)  # warm (page in)
+    V = int(np.prod(dims))
+    oracle.hop(U, psi, bc)  # warm (page in)
     n, t0 = 0, time.perf_counter()
     while True:
-        oracle.hop(U, b, bc)
+        oracle.hop(U, psi, bc)
         n += 1
         el = time.perf_counter() - t0
         if el > budget_s or n >= 20:
@@ -91,7 +97,7 @@ def cpu_baseline(U, b, budget_s=12.0):
     per = el / n
     return {"value": V * 1536 / per / 1e9, "unit": "GB/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{n} FP64 full-lattice hops D psi on {DIMS[0]}^3x{DIMS[3]} (1 rhs), "
+            "sample": f"{n} FP64 full-lattice hops D psi on {dims[0]}^3x{dims[3]} (1 rhs), "
                       f"{per:.3f} s each; bytes counted as the GPU FP64 18-real hop "
                       f"(1536 B per output site)"}
 
@@ -430,6 +436,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
+    ap.add_argument("--no-alt", action="store_true",
+                    help="skip the other multi-rhs solver (block CG vs lockstep)")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 32^3x64 FP16 workload")
     ap.add_argument("--mode", default="solve", choices=["solve", "hop", "copy", "workloads"])
     ap.add_argument("--workloads", default="mixed,force,clover,hmc,multishift,quenched",
                     help="workloads mode: any of mixed, force, clover, hmc, multishift, "
@@ -463,24 +472,26 @@ def main():
 
     assert torch.cuda.is_available()
     dev = torch.device("cuda:0")
-    log(f"generating {DIMS} links (seed 0)")
+    log(f"generating {DIMS} links (seed 0, device generator)")
     t0 = time.perf_counter()
-    U = Synth(0, device=dev).gauge(DIMS)
+    U = Synth(0, device=dev, rng="torch").gauge(DIMS)
     b = point_sources(DIMS, device=dev)
-    log(f"fields ready in {time.perf_counter() - t0:.1f} s")
     bc = bc_phases((0, 0, 0, np.pi))
-    lat = cola.Lattice(DIMS, KAPPA, bc, 0.0, cola.COLA_FLAG_TIMING)
+    lat = cola.Lattice(DIMS, KAPPA_C, bc, CSW, cola.COLA_FLAG_TIMING)
     lat.set_gauge(U)
     assert lat.gauge_is_su3
+    log(f"fields and clover blocks ready in {time.perf_counter() - t0:.1f} s")
     tune = args.tune and args.warmup > 0  # tuning stays out of the timed steps
     if tune:
         cola.cola_set_tuning(lat.h, 1)  # launch shapes measured on first use (warmup)
+    block = args.block
 
-    def solve():
-        return lat.cg(b, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP16_DEFECT, tol=TOL)
+    def solve(blk):
+        return lat.cg(b, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP32_DEFECT, tol=TOL,
+                      block=blk)
 
     for w in range(args.warmup):
-        _, info = solve()
+        _, info = solve(block)
         log(f"warmup {w}: {info['iterations']} inner iterations, {info['outer_cycles']} cycles, "
             f"{info['seconds']:.3f} s, status {info['status']}")
     lat.reset_stats()
@@ -488,40 +499,70 @@ def main():
     t0 = time.perf_counter()
     infos = []
     for k in range(args.steps):
-        x, info = solve()
+        x, info = solve(block)
         infos.append(info)
         log(f"step {k}: {info['iterations']} it, {info['outer_cycles']} cycles, "
             f"{info['seconds']:.3f} s, max residual {max(info['true_rel_residual']):.2e}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    st16 = lat.stats(cola.COLA_FP16)
+    st32 = lat.stats(cola.COLA_FP32)
     st64 = lat.stats(cola.COLA_FP64)
     ms_per_step = wall / args.steps * 1e3
-    achieved = st16["hop_bytes"] / st16["hop_seconds"] / 1e9
-    per_launch_ms = st16["hop_seconds"] / st16["hop_launches"] * 1e3
     ok = all(i["status"] == cola.COLA_OK for i in infos)
+    del x
+    # the dominant kernel: the FP32 12-rhs hop with the clover epilogue (t_o = A^-1 D p),
+    # 2688 B per site of links and spinors plus the 288 B clover block it reads
+    kc = st32["kinds"].get(cola.COLA_HOP_CLOV, {"launches": 0, "seconds": 0.0, "bytes": 0.0})
+    achieved = kc["bytes"] / kc["seconds"] / 1e9 if kc["seconds"] else 0.0
+    per_launch_ms = kc["seconds"] / max(1, kc["launches"]) * 1e3
+    blended = st32["hop_bytes"] / st32["hop_seconds"] / 1e9 if st32["hop_seconds"] else None
+    kinds = {str(k): {"launches": v["launches"],
+                      "avg_ms": round(v["seconds"] / v["launches"] * 1e3, 4),
+                      "GBs": round(v["bytes"] / v["seconds"] / 1e9, 1)}
+             for k, v in st32["kinds"].items()}
+
+    alt = None
+    if not args.no_alt:
+        # the other multi-rhs solver on the same workload (one warm-up, one timed solve)
+        solve(1 - block)
+        torch.cuda.synchronize()
+        _, ia = solve(1 - block)
+        alt = {"solver": "block CG" if block == 0 else "lockstep", "seconds_per_source":
+               ia["seconds"] / 12, "iterations": ia["iterations"],
+               "outer_cycles": ia["outer_cycles"], "status": ia["status"],
+               "max_true_rel_residual": max(ia["true_rel_residual"])}
+        log(f"{alt['solver']}: {ia['iterations']} it, {ia['seconds']:.3f} s")
 
     fp64 = None
     if not args.no_fp64:
-        lat64 = cola.Lattice(DIMS, KAPPA, bc, 0.0, cola.COLA_FLAG_TIMING)
-        lat64.set_gauge(U)
-        if tune:
-            cola.cola_set_tuning(lat64.h, 1)
         b1 = b[:1].clone()
-        lat64.cg(b1, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP64, tol=TOL)  # warm
-        lat64.reset_stats()
-        _, i64 = lat64.cg(b1, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP64, tol=TOL)
-        s64 = lat64.stats(cola.COLA_FP64)
+        lat.cg(b1, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP64, tol=TOL)  # warm
+        lat.reset_stats()
+        _, i64 = lat.cg(b1, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP64, tol=TOL)
+        s64 = lat.stats(cola.COLA_FP64)
         fp64 = {"seconds_per_source": i64["seconds"], "iterations": i64["iterations"],
                 "hop_GBs": s64["hop_bytes"] / s64["hop_seconds"] / 1e9,
                 "true_rel_residual": i64["true_rel_residual"][0]}
         log(f"FP64 single-source CG: {i64['iterations']} it, {i64['seconds']:.3f} s")
-        lat64.close()
+        del b1
+    lat.close()
+    del b
+    torch.cuda.empty_cache()
+
+    c3 = None
+    if not args.no_c3:
+        c3 = fp16_workload(args)
 
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline")
-        cpu = cpu_baseline(U.cpu().numpy(), b[0].cpu().numpy())
+        Uc = U.cpu().numpy()
+        del U
+        # a point source: the values do not change the oracle's cost
+        psi = np.zeros(tuple(reversed(DIMS)) + (4, 3), dtype=np.complex128)
+        psi[0, 0, 0, 0, 0, 0] = 1.0
+        cpu = cpu_baseline(Uc, psi, DIMS)
+        del Uc, psi
 
     per_source = ms_per_step / 1e3 / 12
     out = {
@@ -535,38 +576,86 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f16-storage/f32 inner, f64 outer",
+        "dtype": "f32 inner (storage and arithmetic), f64 outer",
         "data": "synthetic",
-        "config": {"workload": "wilson_eo_32x32x32x64_12rhs_fp16defect", "lattice": list(DIMS),
-                   "kappa": KAPPA, "nrhs": 12, "sources": "point (12 spin-colour at origin)",
-                   "solver": "lockstep 12-RHS CG, FP16 storage + FP64 defect correction",
+        "config": {"workload": WORKLOAD, "lattice": list(DIMS), "kappa": KAPPA_C, "csw": CSW,
+                   "nrhs": 12, "sources": "point (12 spin-colour at origin)",
+                   "solver": ("block CG" if block else "lockstep 12-RHS CG")
+                             + ", FP32 inner + FP64 defect correction, even-odd clover Schur",
                    "tol": TOL, "parallelism": "none (1 GPU)",
                    "launch_shapes": "autotuned in warmup" if tune else "library defaults"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(), "hop_sources_sha256": hop_sources_sha256(),
-                     "kernel": "hop_kernel FP16 12-real links, 12 rhs",
-                     "bytes_per_launch": st16["hop_bytes"] / max(1, st16["hop_launches"]),
+                     "kernel": "hop_kernel FP32 12-real links, 12 rhs, clover epilogue "
+                               "(A^-1 D p)",
+                     "bytes_per_launch": kc["bytes"] / max(1, kc["launches"]),
                      "avg_launch_ms": round(per_launch_ms, 4),
-                     "launches": st16["hop_launches"],
-                     # the same launches against the vector ALU: 1320 flops per site and rhs
-                     # (+ row rebuilds, epilogues) over non-packed FP32 peak (78.6 TF/s)
-                     "alu": {"achieved_TFs": round(st16["hop_flops"] / st16["hop_seconds"]
-                                                   / 1e12, 2),
-                             "peak_TFs": FP32_VALU_PEAK_TFS,
-                             "frac": round(st16["hop_flops"] / st16["hop_seconds"] / 1e12
-                                           / FP32_VALU_PEAK_TFS, 4)}},
+                     "launches": kc["launches"]},
+        "hop_fp32_all_launches": {"GBs": round(blended, 1) if blended else None,
+                                  "launches": st32["hop_launches"],
+                                  "TFs": round(st32["hop_flops"] / st32["hop_seconds"] / 1e12, 2)
+                                  if st32["hop_seconds"] else None,
+                                  "by_kind": kinds},
         "cg": {"seconds_per_source": per_source, "all_converged": ok,
                "inner_iterations": infos[-1]["iterations"], "outer_cycles": infos[-1]["outer_cycles"],
                "max_true_rel_residual": max(max(i["true_rel_residual"]) for i in infos),
                "fp64_outer_hop_GBs": (st64["hop_bytes"] / st64["hop_seconds"] / 1e9
                                       if st64["hop_seconds"] else None)},
+        "other_solver": alt,
         "fp64_single_rhs": fp64,
         "speedup_per_source_vs_fp64": (fp64["seconds_per_source"] / per_source) if fp64 else None,
+        "fp16_32x32x32x64": c3,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def fp16_workload(args):
+    """The 32^3 x 64 plain-Wilson workload with FP16 storage (the spin projection in packed
+    FP16 arithmetic, SU(3) products of FP16 pairs summed in FP32, FP32 elsewhere) inside FP64
+    defect correction, 12 point sources, against one FP64 source."""
+    import torch
+
+    from paper_2302_00850_amd import cola
+    from paper_2302_00850_amd.synth import Synth, bc_phases, point_sources
+
+    dev = torch.device("cuda:0")
+    U = Synth(0, device=dev).gauge(DIMS3)
+    b = point_sources(DIMS3, device=dev)
+    lat = cola.Lattice(DIMS3, KAPPA, bc_phases((0, 0, 0, np.pi)), 0.0, cola.COLA_FLAG_TIMING)
+    lat.set_gauge(U)
+
+    def solve(scheme, rhs):
+        return lat.cg(rhs, system=cola.COLA_SYS_SCHUR, scheme=scheme, tol=TOL)
+
+    solve(cola.COLA_CG_FP16_DEFECT, b)
+    lat.reset_stats()
+    torch.cuda.synchronize()
+    n = 3
+    t0 = time.perf_counter()
+    for _ in range(n):
+        _, info = solve(cola.COLA_CG_FP16_DEFECT, b)
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / n / 12
+    st = lat.stats(cola.COLA_FP16)
+    kp = st["kinds"].get(cola.COLA_HOP_PLAIN)
+    b1 = b[:1].clone()
+    solve(cola.COLA_CG_FP64, b1)
+    _, i64 = solve(cola.COLA_CG_FP64, b1)
     lat.close()
+    log(f"32^3x64 FP16: {per * 12:.3f} s per 12 sources, FP64 {i64['seconds']:.3f} s per source")
+    return {"workload": "wilson_eo_32x32x32x64_12rhs_fp16defect",
+            "dtype": "f16 storage; spin projection in packed f16 arithmetic, SU(3) products "
+                     "of f16 pairs summed in f32, f32 elsewhere; f64 outer",
+            "seconds_per_source": per, "inner_iterations": info["iterations"],
+            "outer_cycles": info["outer_cycles"],
+            "max_true_rel_residual": max(info["true_rel_residual"]),
+            "plain_hop_GBs": kp["bytes"] / kp["seconds"] / 1e9 if kp else None,
+            "plain_hop_avg_ms": kp["seconds"] / kp["launches"] * 1e3 if kp else None,
+            "all_hops_GBs": st["hop_bytes"] / st["hop_seconds"] / 1e9,
+            "fp64_seconds_per_source": i64["seconds"],
+            "speedup_per_source_vs_fp64": i64["seconds"] / per}
 
 
 if __name__ == "__main__":

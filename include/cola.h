@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define COLA_ABI_VERSION 1
+#define COLA_ABI_VERSION 2
 
 /* status codes */
 enum {
@@ -134,6 +134,19 @@ typedef struct {
     double seconds;            /* wall time of the solve                                */
 } cola_cg_result_t;
 
+/* Kinds of hop launch (the epilogue fused into the half-lattice hop D_{p,1-p}), the second
+ * index of the per-kind accounting below.  x: a same-parity spinor, C: clover blocks. */
+enum {
+    COLA_HOP_PLAIN = 0,        /* out = D in                                             */
+    COLA_HOP_XPAY = 1,         /* out = x + a D in                                       */
+    COLA_HOP_CLOV = 2,         /* out = C D in                                           */
+    COLA_HOP_CLOV_XPAY = 3,    /* out = C x + a D in                                     */
+    COLA_HOP_XPAY_CLOV = 4,    /* out = C (x + a D in)                                   */
+    COLA_HOP_XPAY_CG = 5,      /* CG update of x and r with x + a D in (nothing stored)  */
+    COLA_HOP_CLOV_XPAY_CG = 6, /* CG update of x and r with C x + a D in                 */
+    COLA_HOP_KINDS = 8
+};
+
 /* Hop-kernel accounting, per storage precision (index COLA_FP64 .. COLA_FP16), filled
  * only for handles created with COLA_FLAG_TIMING.  Algorithmic bytes count every
  * link, input spinor and output spinor of a launch once (plus the epilogue's extra
@@ -144,6 +157,10 @@ typedef struct {
     double hop_seconds[4];     /* summed HIP-event durations, on the launch stream     */
     double hop_bytes[4];       /* summed algorithmic bytes                             */
     double hop_flops[4];       /* summed flops                                         */
+    /* the same per precision and launch kind (COLA_HOP_*) */
+    long long kind_launches[4][COLA_HOP_KINDS];
+    double kind_seconds[4][COLA_HOP_KINDS];
+    double kind_bytes[4][COLA_HOP_KINDS];
 } cola_stats_t;
 
 /* ---------------------------------------------------------------- lifecycle */
@@ -187,14 +204,20 @@ int cola_unpack_spinor(cola_handle_t *h, void *dst_canon, const void *src_packed
 
 /* -------------------------------------------------------------- hot path */
 
-/* out = op(in) on packed fields of precision `prec` with nrhs right-hand sides.
+/* The fermion matrix applied to a fermion field (the paper's GPU "fermion matrix
+ * inverter" is built on it; its remark that lattice codes are memory-bandwidth bound is
+ * why the stencil stores 12-real links and FP16/FP32 spinors).
+ * out = op(in) on packed fields of precision `prec` with nrhs right-hand sides.
  * HOP/HOP_DAG: in is the parity (1-parity) block, out the `parity` block.
  * M/MDAG/MDAGM: full-lattice fields.  SCHUR*: even-parity blocks (parity ignored).
  * out and in must not overlap.  Asynchronous on `stream`. */
 int cola_dslash_apply(cola_handle_t *h, void *out, const void *in, int op, int parity, int prec,
                       int nrhs, void *stream);
 
-/* Solve for nrhs right-hand sides; x and b are canonical complex128 device arrays
+/* Conjugate-gradient solve with the fermion matrix (the paper's linear-system solvers and
+ * its GPU CG benchmark: 32-bit inner iterations inside a 64-bit outer solver, after the
+ * mixed-precision methods of Clark et al. that it cites).
+ * Solve for nrhs right-hand sides; x and b are canonical complex128 device arrays
  * [nrhs][Lt][Lz][Ly][Lx][4][3].  For COLA_SYS_SCHUR only the even sites of b are
  * read and the odd sites of x are set to zero.  Synchronises `stream`.  Returns
  * COLA_OK, COLA_NOT_CONVERGED (x = best iterate) or COLA_BREAKDOWN, or < 0.
@@ -219,12 +242,28 @@ int cola_cg_solve(cola_handle_t *h, void *x, const void *b, int nrhs, const cola
 int cola_cg_multishift(cola_handle_t *h, void *x, const void *b, int nshift, const double *shifts,
                        const cola_cg_params_t *p, cola_cg_result_t *r, void *stream);
 
-/* Fermion force of S = phi^H (M^H M)^{-1} phi for plain Wilson M, from X = (M^H M)^{-1} phi
+/* The HMC fermion force (the paper's gauge-field generation by Hybrid Monte Carlo, after
+ * Duane et al., in its list of key algorithms): link-wise outer products of two solve
+ * vectors.
+ * Fermion force of S = phi^H (M^H M)^{-1} phi for plain Wilson M, from X = (M^H M)^{-1} phi
  * and Y = M X (canonical complex128 spinors, nrhs = 1).  F: canonical gauge-shaped
  * complex128 output [Lt][Lz][Ly][Lx][4][3][3].  COLA_EINVAL when csw != 0 (the clover
  * term's own force is not implemented).  Asynchronous on `stream`. */
 int cola_fermion_force(cola_handle_t *h, void *F_dev, const void *X_dev, const void *Y_dev,
                        int mode, void *stream);
+
+/* Pseudofermion action S = phi^H (M^H M)^{-1} phi of plain Wilson M on the handle's gauge
+ * field (the action whose derivative the HMC fermion force is; the paper's list of key
+ * algorithms, HMC after Duane et al.): X = (M^H M)^{-1} phi by FP64 CG from x = 0 to the
+ * FP64 true relative residual tol, Y = M X, and *S = Re <phi, X> (host double) from a
+ * deterministic device reduction.  phi, X, Y: canonical complex128 device spinors
+ * [Lt][Lz][Ly][Lx][4][3]; X and Y are written (the inputs of cola_fermion_force).
+ * *iterations (may be NULL) receives the CG iteration count.  Returns COLA_OK,
+ * COLA_NOT_CONVERGED or COLA_BREAKDOWN from the solve (X, Y and S are filled from the last
+ * iterate), COLA_EINVAL for null pointers, tol <= 0 or csw != 0, COLA_ESTATE without a
+ * gauge field.  Synchronises `stream`. */
+int cola_fermion_action(cola_handle_t *h, const void *phi_dev, void *X_dev, void *Y_dev,
+                        double tol, double *S, int *iterations, void *stream);
 
 /* -------------------------------------------------------------------- HMC */
 /* Hybrid Monte Carlo (the paper's gauge-field generation algorithm, after Duane et al.,

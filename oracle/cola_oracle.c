@@ -29,7 +29,28 @@
  * pinned by tree-level O(a) improvement: in a constant abelian field, c_sw = 1
  * cancels the Wilson term's shift of the would-be zero modes.  Every function
  * here is pinned by closed forms, invariants or brute force in the CPU
- * test-suite.
+ * test-suite:
+ *   oracle_gamma          Clifford algebra, gamma5 = diag(1,1,-1,-1)
+ *                         (tests/test_oracle_operator.py: test_gamma_table_clifford)
+ *   oracle_hop, oracle_apply_M
+ *                         free-field symbol and eigenvalues, gamma5-hermiticity, gauge and
+ *                         translation covariance, dense 2^4 assembly, extent-2 directions
+ *                         (tests/test_oracle_operator.py)
+ *   oracle_hop_sites      every site equals oracle_hop (tests/test_oracle_pins.py)
+ *   oracle_apply_M_sites  its own per-site clover assembly against oracle_apply_M fed
+ *                         oracle_clover, every site, csw 0 and 1, both dagger forms
+ *                         (tests/test_oracle_pins.py)
+ *   oracle_apply_schur    dense Schur complement (test_oracle_operator.py)
+ *   oracle_field_strength, oracle_clover
+ *                         U = 1, Hermiticity, chiral blocks, covariance, abelian-flux closed
+ *                         form, tree-level O(a) cancellation (tests/test_oracle_clover_force.py)
+ *   oracle_site_inverse   dense inverses (test_oracle_solver.py, clover propagator)
+ *   oracle_cg             dense LU on 2^4 and 2x2x2x4, free-field FFT propagator
+ *                         (tests/test_oracle_solver.py)
+ *   oracle_force          finite differences of dense solves, Y = eta, S = |eta|^2, covariance
+ *                         (tests/test_oracle_clover_force.py)
+ *   oracle_plaquette      U = 1, constant abelian flux per plane, gauge invariance, the numpy
+ *                         plaquette action of the HMC oracle (tests/test_oracle_pins.py)
  */
 #include <complex.h>
 #include <math.h>

@@ -29,6 +29,8 @@ COLA_SYS_MDAGM, COLA_SYS_SCHUR, COLA_SYS_PROPAGATOR = 0, 1, 2
 COLA_CG_FP64, COLA_CG_FP32_RELIABLE, COLA_CG_FP16_DEFECT, COLA_CG_FP32_DEFECT = 0, 1, 2, 3
 COLA_FLAG_TIMING = 1
 COLA_FORCE_GRAD, COLA_FORCE_LIE = 0, 1
+(COLA_HOP_PLAIN, COLA_HOP_XPAY, COLA_HOP_CLOV, COLA_HOP_CLOV_XPAY, COLA_HOP_XPAY_CLOV,
+ COLA_HOP_XPAY_CG, COLA_HOP_CLOV_XPAY_CG) = range(7)
 MAX_RHS = 16
 
 
@@ -68,9 +70,15 @@ class HmcResult(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+HOP_KINDS = 8
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("hop_launches", ctypes.c_longlong * 4), ("hop_seconds", ctypes.c_double * 4),
-                ("hop_bytes", ctypes.c_double * 4), ("hop_flops", ctypes.c_double * 4)]
+                ("hop_bytes", ctypes.c_double * 4), ("hop_flops", ctypes.c_double * 4),
+                ("kind_launches", (ctypes.c_longlong * HOP_KINDS) * 4),
+                ("kind_seconds", (ctypes.c_double * HOP_KINDS) * 4),
+                ("kind_bytes", (ctypes.c_double * HOP_KINDS) * 4)]
 
 
 EXPORTS = ["cola_abi_version", "cola_create", "cola_destroy", "cola_last_error", "cola_set_gauge",
@@ -78,7 +86,7 @@ EXPORTS = ["cola_abi_version", "cola_create", "cola_destroy", "cola_last_error",
            "cola_dslash_apply", "cola_cg_solve", "cola_fermion_force", "cola_get_stats",
            "cola_reset_stats", "cola_set_tuning", "cola_tune_dump", "cola_gauge_force",
            "cola_gauge_action", "cola_link_update", "cola_momentum_update",
-           "cola_hmc_trajectory", "cola_cg_multishift"]
+           "cola_hmc_trajectory", "cola_cg_multishift", "cola_fermion_action"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -109,6 +117,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cola_cg_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(CgParams),
                                   ctypes.POINTER(CgResult), _vp]
     lib.cola_fermion_force.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, _vp]
+    lib.cola_fermion_action.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double,
+                                        ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int), _vp]
     lib.cola_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
     lib.cola_reset_stats.argtypes = [_vp]
     lib.cola_set_tuning.argtypes = [_vp, ctypes.c_int]
@@ -190,6 +201,15 @@ def cola_cg_solve(h, x, b, nrhs, params: CgParams, result: CgResult, stream=None
 
 def cola_fermion_force(h, F, X, Y, mode, stream=None):
     return _check(h, load().cola_fermion_force(h, F, X, Y, mode, stream))
+
+
+def cola_fermion_action(h, phi, X, Y, tol, stream=None):
+    """(status, S, iterations) of S = Re <phi, X>, X = (M^H M)^{-1} phi, Y = M X."""
+    S = ctypes.c_double()
+    it = ctypes.c_int()
+    rc = _check(h, load().cola_fermion_action(h, phi, X, Y, float(tol), ctypes.byref(S),
+                                              ctypes.byref(it), stream))
+    return rc, S.value, it.value
 
 
 def cola_cg_multishift(h, x, b, nshift, shifts, params: CgParams, result: CgResult,
@@ -431,13 +451,21 @@ class Lattice:
         return {k: getattr(r, k) for k, _ in HmcResult._fields_}
 
     def stats(self, prec=None) -> dict:
-        """Hop accounting for one precision, or summed over all when prec is None."""
+        """Hop accounting for one precision, or summed over all when prec is None; "kinds"
+        splits it by launch kind (COLA_HOP_*: launches, seconds, algorithmic bytes)."""
         s = cola_get_stats(self.h)
         idx = range(4) if prec is None else [prec]
+        kinds = {}
+        for k in range(HOP_KINDS):
+            n = sum(s.kind_launches[i][k] for i in idx)
+            if n:
+                kinds[k] = {"launches": n, "seconds": sum(s.kind_seconds[i][k] for i in idx),
+                            "bytes": sum(s.kind_bytes[i][k] for i in idx)}
         return {"hop_launches": sum(s.hop_launches[i] for i in idx),
                 "hop_seconds": sum(s.hop_seconds[i] for i in idx),
                 "hop_bytes": sum(s.hop_bytes[i] for i in idx),
-                "hop_flops": sum(s.hop_flops[i] for i in idx)}
+                "hop_flops": sum(s.hop_flops[i] for i in idx),
+                "kinds": kinds}
 
     def reset_stats(self):
         cola_reset_stats(self.h)
@@ -446,7 +474,8 @@ class Lattice:
 class PseudofermionAction(torch.autograd.Function):
     """S(U) = phi^H (M^H M)^{-1} phi for plain Wilson M; backward gives dS/dU.
 
-    forward: X = (M^H M)^{-1} phi by FP64 CG, Y = M X, S = Re <phi, X>.
+    forward: one cola_fermion_action call (X = (M^H M)^{-1} phi by FP64 CG, Y = M X,
+    S = Re <phi, X>, all on the device).
     backward: grad_U = gS * (dS/dRe U + i dS/dIm U) from the link-wise adjoint
     kernel; phi receives no gradient.
     """
@@ -454,18 +483,18 @@ class PseudofermionAction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, U, phi, lattice: Lattice, tol=1e-12):
         lattice.set_gauge(U.detach())
-        X, info = lattice.cg(phi.detach().reshape((1,) + lattice.site_shape + (4, 3)),
-                             system=COLA_SYS_MDAGM, scheme=COLA_CG_FP64, tol=tol)
-        if info["status"] != COLA_OK:
-            raise ColaError(info["status"], f"CG did not converge: {info}")
-        X = X.reshape(phi.shape)
-        packed = lattice.pack(X, COLA_FP64, -1)
-        Yp = torch.zeros_like(packed)
-        lattice.dslash(Yp, packed, COLA_OP_M, -1, COLA_FP64, 1)
-        Y = lattice.unpack(Yp, COLA_FP64, 1, -1).reshape(phi.shape)
+        phi_c = phi.detach().contiguous()
+        if lattice._spinor_rhs(phi_c) != 1:
+            raise ValueError("phi must be one canonical spinor")
+        X = torch.empty_like(phi_c)
+        Y = torch.empty_like(phi_c)
+        rc, S, iters = cola_fermion_action(lattice.h, _ptr(phi_c), _ptr(X), _ptr(Y), tol,
+                                           _stream())
+        if rc != COLA_OK:
+            raise ColaError(rc, f"CG did not converge in {iters} iterations")
         ctx.lattice = lattice
         ctx.save_for_backward(X, Y)
-        return torch.vdot(phi.detach().reshape(-1), X.reshape(-1)).real
+        return torch.tensor(S, dtype=torch.float64, device=phi.device)
 
     @staticmethod
     def backward(ctx, gS):

@@ -68,7 +68,7 @@ struct cola_handle {
     // timing of hop launches
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
     std::vector<double> pending_bytes, pending_flops;
-    std::vector<int> pending_prec;
+    std::vector<int> pending_prec, pending_epi;
     std::vector<hipEvent_t> event_pool;
     cola_stats_t stats{};
 

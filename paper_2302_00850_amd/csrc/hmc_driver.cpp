@@ -160,6 +160,44 @@ int cola_gauge_force(cola_handle_t *h, void *F, const void *U, double beta, void
     return COLA_OK;
 }
 
+int cola_fermion_action(cola_handle_t *h, const void *phi, void *X, void *Y, double tol,
+                        double *S, int *iterations, void *stream) {
+    if (!h) return COLA_EINVAL;
+    if (!phi || !X || !Y || !S) return set_error(h, COLA_EINVAL, "null pointer");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return set_error(h, COLA_EINVAL, "need tol > 0");
+    if (h->csw != 0.0)
+        return set_error(h, COLA_EINVAL, "the action's force exists for plain Wilson only");
+    if (!h->gauge_set) return set_error(h, COLA_ESTATE, "no gauge field set");
+    hipStream_t st = hstream(stream);
+    void *Xp, *Yp;
+    double *sc;
+    const size_t pb = cola_field_bytes(h, COLA_FP64, 1, -1);
+    COLA_TRY(get_vec(h, "fa_Xp", pb, &Xp));
+    COLA_TRY(get_vec(h, "fa_Yp", pb, &Yp));
+    COLA_TRY(scalars(h, &sc));
+    // X = (M^H M)^{-1} phi from x = 0
+    cola_cg_params_t cp{};
+    cp.system = COLA_SYS_MDAGM;
+    cp.scheme = COLA_CG_FP64;
+    cp.tol = tol;
+    cp.max_iter = 100000;
+    cp.reliable_interval = 50;
+    double res = 0.0;
+    cola_cg_result_t cr{};
+    cr.true_rel_residual = &res;
+    COLA_TRY(cola_cg_solve(h, X, phi, 1, &cp, &cr, st));
+    if (iterations) *iterations = cr.iterations;
+    // Y = M X through the packed FP64 field; S = Re <phi, X>
+    COLA_TRY(cola_pack_spinor(h, Xp, X, COLA_FP64, 1, -1, st));
+    COLA_TRY(cola_dslash_apply(h, Yp, Xp, COLA_OP_M, -1, COLA_FP64, 1, st));
+    COLA_TRY(cola_unpack_spinor(h, Y, Yp, COLA_FP64, 1, -1, st));
+    COLA_HIP(h, launch_redot(phi, X, (size_t)2 * h->g.Vh * 12, h->partial, sc + 3, st));
+    int rc = COLA_OK;
+    *S = read_scalar(h, sc + 3, st, &rc);
+    COLA_TRY(rc);
+    return cr.status == COLA_OK ? COLA_OK : cr.status;
+}
+
 int cola_gauge_action(cola_handle_t *h, const void *U, double beta, double *S, void *stream) {
     if (!h) return COLA_EINVAL;
     if (!U || !S) return set_error(h, COLA_EINVAL, "null pointer");

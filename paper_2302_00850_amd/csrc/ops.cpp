@@ -372,10 +372,14 @@ int flush_timing(cola_handle_t *h, bool wait_all) {
         float ms = 0;
         COLA_HIP(h, hipEventElapsedTime(&ms, pr.first, pr.second));
         const int pi = h->pending_prec[done];
+        const int ek = h->pending_epi[done];
         h->stats.hop_launches[pi] += 1;
         h->stats.hop_seconds[pi] += ms * 1e-3;
         h->stats.hop_bytes[pi] += h->pending_bytes[done];
         h->stats.hop_flops[pi] += h->pending_flops[done];
+        h->stats.kind_launches[pi][ek] += 1;
+        h->stats.kind_seconds[pi][ek] += ms * 1e-3;
+        h->stats.kind_bytes[pi][ek] += h->pending_bytes[done];
         h->event_pool.push_back(pr.first);
         h->event_pool.push_back(pr.second);
     }
@@ -383,6 +387,7 @@ int flush_timing(cola_handle_t *h, bool wait_all) {
     h->pending_bytes.erase(h->pending_bytes.begin(), h->pending_bytes.begin() + done);
     h->pending_flops.erase(h->pending_flops.begin(), h->pending_flops.begin() + done);
     h->pending_prec.erase(h->pending_prec.begin(), h->pending_prec.begin() + done);
+    h->pending_epi.erase(h->pending_epi.begin(), h->pending_epi.begin() + done);
     return COLA_OK;
 }
 
@@ -432,6 +437,7 @@ int hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, hipStream_t st) 
         h->pending_bytes.push_back(b);
         h->pending_flops.push_back(f);
         h->pending_prec.push_back(prec);
+        h->pending_epi.push_back(c.epi);
     }
     return COLA_OK;
 }

@@ -44,7 +44,7 @@ def test_binding_lists_every_declared_symbol():
 def test_abi_version_and_argument_checks(lib):
     # calls that touch no device: version, null-handle and bad-argument paths
     lib.cola_abi_version.restype = ctypes.c_int
-    assert lib.cola_abi_version() == 1
+    assert lib.cola_abi_version() == 2
     lib.cola_destroy.argtypes = [ctypes.c_void_p]
     assert lib.cola_destroy(None) == -1
     lib.cola_last_error.restype = ctypes.c_char_p
