@@ -701,11 +701,12 @@ int cg_solve_impl(cola_handle_t *h, void *x, const void *b, int nrhs, const cola
         if (!(tr[q] <= thr[q]) && o.status == COLA_OK) o.status = COLA_NOT_CONVERGED;
 
     if (p->system == COLA_SYS_PROPAGATOR) {
-        // x_o = A_oo^-1 (b_o + kappa D_oe x_e); residual of M x = b on the full lattice
-        void *xfull, *mx, *rf;
+        // x_o = A_oo^-1 (b_o + kappa D_oe x_e); residual of M x = b on the full lattice,
+        // one parity block at a time in the solver's FP64 residual block:
+        // t = A_pp x_p - kappa D x_{1-p}, then t = b_p - t
+        void *xfull, *t;
         COLA_TRY(get_vec(h, "prop_x_full_" + std::to_string(nrhs), 2 * bb64, &xfull));
-        COLA_TRY(get_vec(h, "prop_mx_" + std::to_string(nrhs), 2 * bb64, &mx));
-        COLA_TRY(get_vec(h, "prop_r_" + std::to_string(nrhs), 2 * bb64, &rf));
+        COLA_TRY(vec(c, "r64", SpinorFmt::F64, &t));
         COLA_HIP(h, hipMemcpyAsync(xfull, x64, bb64, hipMemcpyDeviceToDevice, st));
         HopCall hc{(char *)xfull + bb64, x64, 1, 0};
         hc.epi = clover ? EPI_XPAY_CLOV : EPI_XPAY;
@@ -713,10 +714,20 @@ int cg_solve_impl(cola_handle_t *h, void *x, const void *b, int nrhs, const cola
         hc.a = h->kappa;
         hc.clov = h->clovinv64;
         COLA_TRY(hop(h, hc, COLA_FP64, nrhs, st));
-        COLA_TRY(apply_op(h, mx, xfull, COLA_OP_M, -1, COLA_FP64, nrhs, st));
-        const Reduce red_r = reduce_into(h, TRUE_RES), red_bf = reduce_into(h, BNORM);
+        const BlasShape sh1 = blas_shape(h->g, nrhs, 1);
+        for (int q = 0; q < 2; ++q) {
+            HopCall hm{t, (const char *)xfull + (1 - q) * bb64, q, 0};
+            hm.epi = clover ? EPI_CLOV_XPAY : EPI_XPAY;
+            hm.x = (const char *)xfull + q * bb64;
+            hm.a = -h->kappa;
+            hm.clov = h->clov64;
+            COLA_TRY(hop(h, hm, COLA_FP64, nrhs, st));
+            COLA_HIP(h, launch_residual(sh1, t, (const char *)bfull + q * bb64, t,
+                                        reduce_into(h, q == 0 ? TRUE_RES : TMP), st));
+        }
+        COLA_HIP(h, launch_scalar_add(c.slot(TRUE_RES), c.slot(TMP), nrhs, st));
+        const Reduce red_bf = reduce_into(h, BNORM);
         const BlasShape shf = blas_shape(h->g, nrhs, 2);
-        COLA_HIP(h, launch_residual(shf, rf, bfull, mx, red_r, st));
         COLA_HIP(h, launch_norm2(shf, SpinorFmt::F64, bfull, red_bf, st));
         COLA_TRY(read_slot(c, TRUE_RES, tr.data()));
         COLA_TRY(read_slot(c, BNORM, bn.data()));

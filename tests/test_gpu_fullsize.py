@@ -16,7 +16,7 @@ import torch
 import oracle
 from oracle import dense
 from paper_2302_00850_amd.synth import Synth, bc_phases, point_sources, unit_gauge
-from tests._util import rel
+from tests._util import assert_close, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -65,7 +65,7 @@ def test_hop_sampled_32x64(prec, nrhs, tol):
     for q in range(nrhs):
         ref = oracle.hop_sites(Uh, src[q], ANTI, sites)
         g = got[q].reshape(-1, 4, 3)[sites]
-        assert rel(g, ref) <= tol, (prec, q)
+        assert_close(g, ref, tol, (prec, q))
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-13), (2, 2e-6)])
@@ -86,7 +86,7 @@ def test_clover_M_sampled_48x96(prec, tol):
     Uh = U.cpu().numpy()
     sites = np.concatenate([_sample_sites(dims, 0, 128, 2), _sample_sites(dims, 1, 128, 3)])
     ref = oracle.apply_M_sites(Uh, src, kappa, ANTI, sites, csw=csw)
-    assert rel(got[sites], ref) <= tol
+    assert_close(got[sites], ref, tol)
 
 
 def _free_prop(b, dims, kappa, theta=(0, 0, 0, np.pi)):
@@ -200,8 +200,8 @@ def test_force_fd_and_oracle_24x48():
     G = lat.force(X[0], Y[0], cola.COLA_FORCE_GRAD).cpu().numpy()
     Uh = U.cpu().numpy()
     Xh, Yh = X.cpu().numpy()[0], Y.cpu().numpy()[0]
-    assert rel(G, oracle.force(Uh, Xh, Yh, kappa, ANTI, mode=0)) <= 1e-12
-    assert rel(F, oracle.force(Uh, Xh, Yh, kappa, ANTI, mode=1)) <= 1e-12
+    assert_close(G, oracle.force(Uh, Xh, Yh, kappa, ANTI, mode=0), 1e-12, "grad", 36)
+    assert_close(F, oracle.force(Uh, Xh, Yh, kappa, ANTI, mode=1), 1e-12, "lie", 36)
 
     rng = np.random.default_rng(11)
     V = int(np.prod(dims))

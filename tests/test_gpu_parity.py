@@ -13,7 +13,7 @@ import torch
 
 import oracle
 from paper_2302_00850_amd.synth import Synth, bc_phases
-from tests._util import rel
+from tests._util import assert_close, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -90,7 +90,7 @@ def test_hop_matches_oracle(fields, prec, parity, dagger, bc, nrhs):
     m_out = _even(DIMS) if parity == 0 else ~_even(DIMS)
     ref = np.where(m_out, ref, 0)
     got = np.where(m_out, got, 0)
-    assert rel(got, ref) <= TOL[prec], (prec, parity, dagger, bc, nrhs)
+    assert_close(got, ref, TOL[prec], (prec, parity, dagger, bc, nrhs))
 
 
 OPS = [(cola.COLA_OP_M, "M"), (cola.COLA_OP_MDAG, "Mdag"), (cola.COLA_OP_MDAGM, "MdagM"),
@@ -138,7 +138,7 @@ def test_operators_match_oracle(fields, op, name, prec, csw):
     if schur:
         got = np.where(_even(DIMS), got, 0)
     tol = TOL[prec] * (4 if name in ("MdagM", "SdagS") else 1)
-    assert rel(got, ref) <= tol, (name, prec, csw)
+    assert_close(got, ref, tol, (name, prec, csw))
 
 
 def test_compressed_links_refused_for_non_su3(fields):
@@ -158,7 +158,7 @@ def test_compressed_links_refused_for_non_su3(fields):
     got = lat.unpack(out, 0, 1, 0).cpu().numpy()[0]
     src = np.where(~_even(DIMS), psi[0], 0)
     ref = np.where(_even(DIMS), oracle.hop(Ub, src, ANTI), 0)
-    assert rel(np.where(_even(DIMS), got, 0), ref) < 1e-13
+    assert_close(np.where(_even(DIMS), got, 0), ref, 1e-13)
 
 
 def test_dslash_argument_errors(fields):
@@ -240,7 +240,7 @@ def test_staged_links_identical(fields, prec, op, monkeypatch):
         got = lat.unpack(ref, prec, nrhs, 0).cpu().numpy()
         src = np.where(~_even(DIMS), lat.unpack(pin, prec, nrhs, 1).cpu().numpy(), 0)
         want = np.where(_even(DIMS), oracle.hop(U, src, GENERIC), 0)
-        assert rel(np.where(_even(DIMS), got, 0), want) <= TOL[prec]
+        assert_close(np.where(_even(DIMS), got, 0), want, TOL[prec])
 
 
 @pytest.mark.parametrize("prec", [2, 3])
@@ -259,7 +259,7 @@ def test_hop_rhs_counts(fields, prec, nrhs):
     got = np.where(_even(DIMS), lat.unpack(out, prec, nrhs, 0).cpu().numpy(), 0)
     src_r = np.where(~_even(DIMS), lat.unpack(pin, prec, nrhs, 1).cpu().numpy(), 0)
     want = np.where(_even(DIMS), oracle.hop(U, src_r, GENERIC), 0)
-    assert rel(got, want) <= TOL[prec]
+    assert_close(got, want, TOL[prec])
 
 
 def test_hop_deterministic_and_timing_stats(fields):

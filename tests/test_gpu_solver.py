@@ -12,7 +12,7 @@ import torch
 
 import oracle
 from paper_2302_00850_amd.synth import Synth, bc_phases, point_sources
-from tests._util import rel
+from tests._util import assert_close, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -71,7 +71,7 @@ def test_cg_fp64_fixed_iterations_match_oracle(fields, system, fuse, monkeypatch
     x, info = lat.cg(_cuda(b[:1]), system=system, scheme=cola.COLA_CG_FP64, tol=1e-300,
                      max_iter=n)
     assert info["iterations"] == n and info["status"] == cola.COLA_NOT_CONVERGED
-    assert rel(x.cpu().numpy()[0], x_ref) <= 1e-12
+    assert_close(x.cpu().numpy()[0], x_ref, 1e-12)
 
 
 SCHEMES = [cola.COLA_CG_FP64, cola.COLA_CG_FP32_RELIABLE, cola.COLA_CG_FP16_DEFECT,
@@ -268,7 +268,7 @@ def test_force_kernel_matches_oracle(fields, mode, bc):
     lat = _lat(U, bcv)
     F = lat.force(_cuda(X), _cuda(Y), mode).cpu().numpy()
     ref = oracle.force(U, X, Y, KAPPA, bcv, mode=mode)
-    assert rel(F, ref) <= 1e-13
+    assert_close(F, ref, 1e-13, "force", 36)
 
 
 def test_pseudofermion_action_autograd(fields):
