@@ -214,6 +214,24 @@ int cola_unpack_spinor(cola_handle_t *h, void *dst_canon, const void *src_packed
 int cola_dslash_apply(cola_handle_t *h, void *out, const void *in, int op, int parity, int prec,
                       int nrhs, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): cola_dslash_apply with the same
+ * arguments, layouts and results (bitwise), which allocates nothing.  The intermediate
+ * vectors of the composed operators (M^H M: one full field; S and S^H: one odd block;
+ * S^H S: an even and an odd block) live in a fixed device workspace of
+ * COLA_NOALLOC_SCRATCH_BYTES (128 MiB) per device, a static array of the library that
+ * each device holds until the process ends; its address is taken at cola_create.
+ * Returns COLA_EINVAL (with a message naming both sizes) when the operator needs more
+ * workspace than that, before touching any buffer.  The hops run in the cached or the
+ * default launch shape: no tuning, no timing events (COLA_FLAG_TIMING is ignored).
+ * Every call on a device shares that device's workspace: calls that overlap on one
+ * device (two streams, two threads, two handles) race, so the caller orders them.
+ * Nothing in the workspace has to start at zero (each intermediate is written in full
+ * before it is read).  Asynchronous on `stream`. */
+#define COLA_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int cola_dslash_apply_noalloc(cola_handle_t *h, void *out, const void *in, int op, int parity,
+                              int prec, int nrhs, void *stream);
+
 /* Conjugate-gradient solve with the fermion matrix (the paper's linear-system solvers and
  * its GPU CG benchmark: 32-bit inner iterations inside a 64-bit outer solver, after the
  * mixed-precision methods of Clark et al. that it cites).

@@ -86,7 +86,8 @@ EXPORTS = ["cola_abi_version", "cola_create", "cola_destroy", "cola_last_error",
            "cola_dslash_apply", "cola_cg_solve", "cola_fermion_force", "cola_get_stats",
            "cola_reset_stats", "cola_set_tuning", "cola_tune_dump", "cola_gauge_force",
            "cola_gauge_action", "cola_link_update", "cola_momentum_update",
-           "cola_hmc_trajectory", "cola_cg_multishift", "cola_fermion_action"]
+           "cola_hmc_trajectory", "cola_cg_multishift", "cola_fermion_action",
+           "cola_dslash_apply_noalloc"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -114,6 +115,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cola_unpack_spinor.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]
     lib.cola_dslash_apply.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, _vp]
+    lib.cola_dslash_apply_noalloc.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_int, _vp]
     lib.cola_cg_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(CgParams),
                                   ctypes.POINTER(CgResult), _vp]
     lib.cola_fermion_force.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, _vp]
@@ -192,6 +195,11 @@ def cola_unpack_spinor(h, dst, src, prec, nrhs, parity, stream=None):
 
 def cola_dslash_apply(h, out, inp, op, parity, prec, nrhs, stream=None):
     return _check(h, load().cola_dslash_apply(h, out, inp, op, parity, prec, nrhs, stream))
+
+
+def cola_dslash_apply_noalloc(h, out, inp, op, parity, prec, nrhs, stream=None):
+    return _check(h, load().cola_dslash_apply_noalloc(h, out, inp, op, parity, prec, nrhs,
+                                                      stream))
 
 
 def cola_cg_solve(h, x, b, nrhs, params: CgParams, result: CgResult, stream=None):

@@ -103,6 +103,12 @@ int cola_create(cola_handle_t **hp, const int dims[4], double kappa, const doubl
         delete h;
         return e == hipErrorOutOfMemory ? COLA_ENOMEM : COLA_EHIP;
     }
+    // the fixed workspace of cola_dslash_apply_noalloc: its address on this device
+    if (scratch_address(h, &h->scratch) != COLA_OK) {
+        free_all(h);
+        delete h;
+        return COLA_EHIP;
+    }
     const char *tune = getenv("COLA_TUNE");
     if (tune) h->tune_mode = atoi(tune);
     *hp = h;
@@ -218,6 +224,30 @@ int cola_dslash_apply(cola_handle_t *h, void *out, const void *in, int op, int p
         return set_error(h, COLA_EINVAL, "HOP needs the output parity 0 or 1");
     COLA_TRY(check_rhs(h, nrhs));
     return apply_op(h, out, in, op, parity, prec, nrhs, as_stream(stream));
+}
+
+int cola_dslash_apply_noalloc(cola_handle_t *h, void *out, const void *in, int op, int parity,
+                              int prec, int nrhs, void *stream) {
+    static_assert(kScratchBytes == COLA_NOALLOC_SCRATCH_BYTES, "workspace size in the header");
+    if (!h) return COLA_EINVAL;
+    if (!out || !in) return set_error(h, COLA_EINVAL, "null pointer");
+    if (out == in) return set_error(h, COLA_EINVAL, "out and in must not overlap");
+    if (!valid_prec(prec)) return set_error(h, COLA_EINVAL, "unknown precision");
+    if (op < COLA_OP_HOP || op > COLA_OP_SCHUR_DAGSCHUR)
+        return set_error(h, COLA_EINVAL, "unknown operator");
+    if ((op == COLA_OP_HOP || op == COLA_OP_HOP_DAG) && (parity < 0 || parity > 1))
+        return set_error(h, COLA_EINVAL, "HOP needs the output parity 0 or 1");
+    COLA_TRY(check_rhs(h, nrhs));
+    const size_t need = op_workspace_bytes(h, op, prec, nrhs);
+    if (need > kScratchBytes)
+        return set_error(h, COLA_EINVAL,
+                         "operator needs " + std::to_string(need) +
+                             " bytes of workspace, above the fixed " +
+                             std::to_string(kScratchBytes) +
+                             "-byte scratch of cola_dslash_apply_noalloc");
+    if (!h->scratch) return set_error(h, COLA_ESTATE, "no workspace address for this device");
+    return apply_op(h, out, in, op, parity, prec, nrhs, as_stream(stream), nullptr,
+                    (char *)h->scratch);
 }
 
 int cola_cg_solve(cola_handle_t *h, void *x, const void *b, int nrhs, const cola_cg_params_t *p,

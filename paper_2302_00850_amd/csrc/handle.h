@@ -16,6 +16,8 @@ namespace cola {
 
 constexpr int kMaxRhs = kRedMaxWidth;
 constexpr int kMaxGrid = kRedMaxBlocks;
+// size of the fixed device workspace of cola_dslash_apply_noalloc (per device)
+constexpr size_t kScratchBytes = (size_t)128 << 20;
 
 struct TuneEntry {
     int rpt = 1;
@@ -72,6 +74,9 @@ struct cola_handle {
     std::vector<hipEvent_t> event_pool;
     cola_stats_t stats{};
 
+    // device address of this device's fixed workspace (cola_dslash_apply_noalloc)
+    void *scratch = nullptr;
+
     // autotuning
     int tune_mode = 0;
     std::map<std::string, cola::TuneEntry> tune;
@@ -122,6 +127,9 @@ struct HopCall {
     const void *cg_p = nullptr;
     const double *cg_rho = nullptr, *cg_pi = nullptr, *cg_pi2 = nullptr;
     const int *cg_active = nullptr;
+    // fixed: no launch-shape tuning, no timing events, no occupancy queries (the
+    // non-allocating entry point); the shape is the cached or the default one
+    bool fixed = false;
 };
 int hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, hipStream_t st);
 
@@ -134,9 +142,15 @@ int schur_normal_cg_step(cola_handle_t *h, int prec, int nrhs, hipStream_t st, v
                          double *rho_new);
 
 // composite operators on packed fields (see COLA_OP_*); norm_result (optional)
-// receives |out|^2 per rhs where the composition allows it to be fused.
+// receives |out|^2 per rhs where the composition allows it to be fused.  ws: a
+// caller-provided workspace of op_workspace_bytes() for the intermediate vectors
+// (the hops then run in their fixed shapes, untimed); nullptr: the handle's cache.
 int apply_op(cola_handle_t *h, void *out, const void *in, int op, int parity, int prec, int nrhs,
-             hipStream_t st, double *norm_result = nullptr);
+             hipStream_t st, double *norm_result = nullptr, char *ws = nullptr);
+size_t op_workspace_bytes(const cola_handle_t *h, int op, int prec, int nrhs);
+
+// device address of this handle's device's fixed workspace (kScratchBytes)
+int scratch_address(cola_handle_t *h, void **out);
 
 // timing bookkeeping
 int flush_timing(cola_handle_t *h, bool wait_all);
