@@ -378,6 +378,72 @@ def workloads_mode(args):
                           "unshifted_cg_iterations": i1["iterations"],
                           "cost_vs_one_solve": ims["seconds"] / i1["seconds"]}), flush=True)
         lat.close()
+    if "eigen" in sel:
+        # the 32 lowest modes of S^H S on 16^3 x 32 near the critical kappa (accelerated CG,
+        # a loose tolerance: the modes serve deflation), then FP64 CG on a Gaussian source
+        # with and without them
+        dims = (16, 16, 16, 32)
+        kappa_e = 0.124
+        s = Synth(0, device="cuda", rng="torch")
+        U = s.gauge(dims)
+        b = s.gaussian_spinor(dims, 1)
+        X0 = torch.cat([s.gaussian_spinor(dims, 16), s.gaussian_spinor(dims, 16)])
+        lat = cola.Lattice(dims, kappa_e, bc, 0.0, cola.COLA_FLAG_TIMING)
+        lat.set_gauge(U)
+        lam, X, ie = lat.eigensolve(X0, system=cola.COLA_SYS_SCHUR, tol=1e-5, max_sweeps=30)
+        _, i0 = solve(lat, b, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP64, tol=TOL)
+        lat.cg_deflated(b, X, lam, system=cola.COLA_SYS_SCHUR, tol=TOL)  # warm
+        torch.cuda.synchronize()
+        _, idf = lat.cg_deflated(b, X, lam, system=cola.COLA_SYS_SCHUR, tol=TOL)
+        print(json.dumps({"workload": "eigen_eo_16x16x16x32_32modes", "lattice": list(dims),
+                          "kappa": kappa_e,
+                          "eigensolve": {"seconds": ie["seconds"], "sweeps": ie["sweeps"],
+                                         "applications": ie["applications"],
+                                         "status": ie["status"], "eigenvalues": lam,
+                                         "max_residual": max(ie["residuals"])},
+                          "cg_fp64": {"seconds": i0["seconds"], "iterations": i0["iterations"]},
+                          "cg_fp64_deflated": {"seconds": idf["seconds"],
+                                               "iterations": idf["iterations"],
+                                               "residual": idf["true_rel_residual"][0]}}),
+              flush=True)
+        lat.close()
+        del X, X0
+        torch.cuda.empty_cache()
+    if "flic" in sel:
+        # FLIC (APE alpha 0.7, 4 sweeps, c_sw 1) on 32^3 x 64: 12 point sources, FP32 inner /
+        # FP64 outer propagator against one FP64 source
+        dims = (32, 32, 32, 64)
+        s = Synth(0, device="cuda", rng="torch")
+        U = s.gauge(dims)
+        b = point_sources(dims, device="cuda")
+        lat = cola.Lattice(dims, 0.118, bc, 1.0, cola.COLA_FLAG_TIMING)
+        lat.set_gauge(U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = lat.ape_smear(U, 0.7, 4)
+        torch.cuda.synchronize()
+        t_ape = time.perf_counter() - t0
+        lat.set_fat_gauge(F)
+        _, i32 = solve(lat, b, system=cola.COLA_SYS_PROPAGATOR, scheme=cola.COLA_CG_FP32_DEFECT,
+                       tol=TOL)
+        g32 = hop_gbs(lat, cola.COLA_FP32)
+        b1 = b[:1].clone()
+        _, i64 = solve(lat, b1, system=cola.COLA_SYS_PROPAGATOR, scheme=cola.COLA_CG_FP64, tol=TOL)
+        g64 = hop_gbs(lat, cola.COLA_FP64)
+        print(json.dumps({"workload": "flic_eo_32x32x32x64_12rhs_fp32defect",
+                          "lattice": list(dims), "ape": {"alpha": 0.7, "sweeps": 4,
+                                                         "seconds": t_ape},
+                          "mixed_12rhs": {"seconds": i32["seconds"],
+                                          "per_source": i32["seconds"] / 12,
+                                          "iterations": i32["iterations"],
+                                          "max_residual": max(i32["true_rel_residual"]),
+                                          "hop_GBs": g32},
+                          "fp64_1rhs": {"seconds": i64["seconds"],
+                                        "iterations": i64["iterations"],
+                                        "residual": i64["true_rel_residual"][0], "hop_GBs": g64},
+                          "speedup_per_source": i64["seconds"] / (i32["seconds"] / 12)}),
+              flush=True)
+        lat.close()
     if "clover" in sel:
         dims = (48, 48, 48, 96)
         s = Synth(0, device="cuda", rng="torch")
@@ -440,16 +506,20 @@ def main():
                     help="skip the other multi-rhs solver (block CG vs lockstep)")
     ap.add_argument("--no-c3", action="store_true", help="skip the 32^3x64 FP16 workload")
     ap.add_argument("--mode", default="solve", choices=["solve", "hop", "copy", "workloads"])
-    ap.add_argument("--workloads", default="mixed,force,clover,hmc,multishift,quenched",
+    ap.add_argument("--workloads",
+                    default="mixed,force,clover,hmc,multishift,quenched,eigen,flic",
                     help="workloads mode: any of mixed, force, clover, hmc, multishift, "
-                         "quenched")
+                         "quenched, eigen, flic")
     ap.add_argument("--block", type=int, default=0, help="use block CG in the multi-RHS solves")
     ap.add_argument("--lattice", default="32,32,32,64", help="hop mode: Lx,Ly,Lz,Lt")
     ap.add_argument("--prec", default="0,2,3", help="hop mode: precisions (0 FP64 .. 3 FP16)")
     ap.add_argument("--nrhs", default="1,12", help="hop mode: right-hand-side counts")
     ap.add_argument("--iters", type=int, default=20, help="hop mode: timed launches")
     ap.add_argument("--tune", action="store_true",
-                    help="autotune hop launch shapes on first use (solve mode: in the warmup)")
+                    help="hop mode: autotune launch shapes on first use")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="solve mode: keep the library's default launch shapes (by default the "
+                         "first warmup tunes every hop shape the solve uses)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -481,7 +551,7 @@ def main():
     lat.set_gauge(U)
     assert lat.gauge_is_su3
     log(f"fields and clover blocks ready in {time.perf_counter() - t0:.1f} s")
-    tune = args.tune and args.warmup > 0  # tuning stays out of the timed steps
+    tune = not args.no_tune and args.warmup > 0  # tuning stays out of the timed steps
     if tune:
         cola.cola_set_tuning(lat.h, 1)  # launch shapes measured on first use (warmup)
     block = args.block

@@ -134,6 +134,26 @@ typedef struct {
     double seconds;            /* wall time of the solve                                */
 } cola_cg_result_t;
 
+typedef struct {
+    int system;             /* COLA_SYS_MDAGM (A = M^H M) or COLA_SYS_SCHUR (A = S^H S on
+                               the even sites)                                          */
+    double tol;             /* stop when |A x_i - lambda_i x_i| <= tol lambda_i for all i */
+    double inner_reduction; /* gradient reduction that ends one vector's minimisation in
+                               a sweep (the acceleration; 0: 0.1)                       */
+    int inner_max;          /* CG steps per vector and sweep at most (0: 50)            */
+    int max_sweeps;         /* sweeps at most (0: 100)                                  */
+} cola_eig_params_t;
+
+typedef struct {
+    int status;          /* COLA_OK or COLA_NOT_CONVERGED (max_sweeps reached)          */
+    int sweeps;          /* sweeps done                                                 */
+    int applications;    /* applications of A                                           */
+    double *eigenvalues; /* caller-owned host array[n] (may be NULL): ascending        */
+    double *residuals;   /* caller-owned host array[n] (may be NULL):
+                            |A x_i - lambda_i x_i| / lambda_i                           */
+    double seconds;      /* wall time                                                   */
+} cola_eig_result_t;
+
 /* Kinds of hop launch (the epilogue fused into the half-lattice hop D_{p,1-p}), the second
  * index of the per-kind accounting below.  x: a same-parity spinor, C: clover blocks. */
 enum {
@@ -260,6 +280,33 @@ int cola_cg_solve(cola_handle_t *h, void *x, const void *b, int nrhs, const cola
 int cola_cg_multishift(cola_handle_t *h, void *x, const void *b, int nshift, const double *shifts,
                        const cola_cg_params_t *p, cola_cg_result_t *r, void *stream);
 
+/* Low eigenmodes (the paper's eigenmode solvers, after Kalkreuter and Simma's
+ * accelerated conjugate-gradient method): the n lowest eigenpairs of A = M^H M or S^H S
+ * by minimising the Rayleigh quotient of one vector at a time by CG, each vector kept
+ * orthogonal to the ones before it, the minimisation of a vector stopped early once its
+ * gradient has fallen by p->inner_reduction, and a Rayleigh-Ritz rotation of the n
+ * vectors after each sweep, until every residual meets p->tol.  FP64 throughout.
+ * X: canonical complex128 [n][Lt][Lz][Ly][Lx][4][3] device array, the starting vectors
+ * on entry (linearly independent; SCHUR reads their even sites) and the orthonormal
+ * eigenvectors on return (SCHUR: odd sites zero), ascending eigenvalues in
+ * r->eigenvalues.  n = 1 .. 32.  Returns COLA_OK, COLA_NOT_CONVERGED (the current
+ * vectors and Ritz values are returned), COLA_BREAKDOWN (dependent or non-finite
+ * starting vectors; X unchanged) or < 0: COLA_EINVAL for another system, n out of
+ * range, tol <= 0 or csw-free requirements unmet, COLA_ESTATE without a gauge field.
+ * Synchronises `stream`. */
+int cola_eigensolve(cola_handle_t *h, void *X, int n, const cola_eig_params_t *p,
+                    cola_eig_result_t *r, void *stream);
+
+/* Deflated CG: cola_cg_solve on the MDAGM or SCHUR system started from the low-mode part
+ * of the solution, x0 = sum_i X_i <X_i, b> / lambda[i], with n eigenpairs of that
+ * system's A (from cola_eigensolve: X canonical complex128 [n][...] device array,
+ * lambda a host array).  Any scheme; p->use_x0 is ignored (x is overwritten with x0 on
+ * entry).  Returns like cola_cg_solve; COLA_EINVAL for the PROPAGATOR system, n out of
+ * 1 .. 32 or a non-positive eigenvalue. */
+int cola_cg_deflated(cola_handle_t *h, void *x, const void *b, int nrhs, const void *X,
+                     const double *lambda, int n, const cola_cg_params_t *p,
+                     cola_cg_result_t *r, void *stream);
+
 /* The HMC fermion force (the paper's gauge-field generation by Hybrid Monte Carlo, after
  * Duane et al., in its list of key algorithms): link-wise outer products of two solve
  * vectors.
@@ -283,6 +330,31 @@ int cola_fermion_force(cola_handle_t *h, void *F_dev, const void *X_dev, const v
 int cola_fermion_action(cola_handle_t *h, const void *phi_dev, void *X_dev, void *Y_dev,
                         double tol, double *S, int *iterations, void *stream);
 
+/* ------------------------------------------------ FLIC (fat-link irrelevant clover)
+ * The CSSM action family the paper's physics programme uses (the FLIC and fat-link HMC
+ * entries of its bibliography): the relevant part of the Wilson-Dirac operator keeps the
+ * thin links U, the irrelevant Wilson and clover terms use APE-smeared links F:
+ *   M psi = A_F psi - kappa sum_mu [(F_mu(x) - g_mu U_mu(x)) e+ psi(x+mu)
+ *                                   + (F_mu(x-mu)^H + g_mu U_mu(x-mu)^H) e- psi(x-mu)]
+ * with A_F the clover matrix of F (csw != 0) or 1.  F = U gives the Wilson(-clover)
+ * operator. */
+
+/* APE smearing: nsweeps sweeps of V_mu(x) = (1 - alpha) U_mu(x) + (alpha / 6) (sum of the
+ * six staples around the link), each projected to the nearest SU(3) matrix (unitary
+ * polar factor, determinant phase removed with the principal cube root).  F and U:
+ * canonical complex128 [Lt][Lz][Ly][Lx][4][3][3] device arrays (F may be U); periodic
+ * links.  nsweeps = 0 copies U.  Asynchronous on `stream`. */
+int cola_ape_smear(cola_handle_t *h, void *F, const void *U, double alpha, int nsweeps,
+                   void *stream);
+
+/* Switch the handle to the FLIC operator with smeared links F (canonical, SU(3) to 1e-12)
+ * and the thin links of the last cola_set_gauge; the clover term (csw != 0) is rebuilt
+ * from F.  Every operator, solver and eigensolver call then applies FLIC, in FP64 and
+ * FP32 (COLA_FP16 is refused); cola_fermion_force and cola_hmc_trajectory refuse it.
+ * cola_set_gauge returns the handle to the Wilson(-clover) operator.  COLA_ESTATE
+ * before cola_set_gauge.  Synchronises `stream`. */
+int cola_set_fat_gauge(cola_handle_t *h, const void *F, void *stream);
+
 /* -------------------------------------------------------------------- HMC */
 /* Hybrid Monte Carlo (the paper's gauge-field generation algorithm, after Duane et al.,
  * in its list of algorithms) for SU(3) links with the Wilson plaquette action
@@ -300,7 +372,9 @@ int cola_gauge_force(cola_handle_t *h, void *F_dev, const void *U_dev, double be
 /* *S = S_g(U) (host double); synchronises `stream`. */
 int cola_gauge_action(cola_handle_t *h, const void *U_dev, double beta, double *S,
                       void *stream);
-/* U <- exp(i eps P) U on every link (in place). */
+/* U <- exp(i eps P) U on every link (in place), each link's rows then re-orthonormalised
+ * (row 2 = conj(row0 x row1)), so that rounding does not move U off SU(3) over many
+ * updates (the compressed link formats require SU(3) to 1e-12). */
 int cola_link_update(cola_handle_t *h, void *U_dev, const void *P_dev, double eps, void *stream);
 /* P -= eps (F1 + F2) on every link (F2 may be NULL). */
 int cola_momentum_update(cola_handle_t *h, void *P_dev, const void *F1_dev, const void *F2_dev,
@@ -357,10 +431,21 @@ int cola_reset_stats(cola_handle_t *h);
  * Keys are (lattice, precision, nrhs, epilogue, fused norm).
  * mode 0: off (defaults), 1: tune on first use of a key (each candidate timed on the
  * caller's buffers, so that first call takes longer), 2: re-tune every key.
- * The table is kept per handle; cola_tune_dump writes it as JSON text into buf
- * (returns the length needed, including the terminating NUL). */
+ * Tuned shapes go into a per-handle table and into a process-wide table kept in a text
+ * file ($COLA_TUNE_CACHE, empty for none; else $XDG_CACHE_HOME/cola/hop_tune.txt or
+ * ~/.cache/cola/hop_tune.txt), one line per (device, key).  With tuning off, a hop takes
+ * the handle's tuned shape, else the stored one (the file is read on the first hop of the
+ * process), else the default: shapes tuned once are used by default afterwards.
+ * COLA_HOP_SHAPE (a measurement knob) overrides the stored shapes.
+ * cola_tune_dump writes the handle's table as JSON text into buf (returns the length
+ * needed, including the terminating NUL). */
 int cola_set_tuning(cola_handle_t *h, int mode);
 size_t cola_tune_dump(const cola_handle_t *h, char *buf, size_t len);
+/* Merge the file at path (NULL: the default file) into the process-wide table, or write
+ * that table there (atomically, creating the directory).  Return the number of entries,
+ * or COLA_EINVAL when the file cannot be read or written. */
+int cola_tune_load(cola_handle_t *h, const char *path);
+int cola_tune_save(cola_handle_t *h, const char *path);
 
 #ifdef __cplusplus
 }

@@ -20,8 +20,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcola.so")
 ARCH = os.environ.get("COLA_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["hop_f64_18.hip", "hop_f64_12.hip", "hop_f32_12.hip", "hop_f16_12.hip", "hop_dispatch.cpp", "pack.hip", "blas.hip", "blas_block.hip", "clover.hip", "force.hip", "hmc.hip", "hmc_driver.cpp", "ops.cpp", "solver.cpp",
-           "scratch.hip", "api.cpp"]
+SOURCES = ["hop_f64_18.hip", "hop_f64_12.hip", "hop_f32_12.hip", "hop_f16_12.hip", "hop_flic.hip", "hop_dispatch.cpp", "pack.hip", "blas.hip", "blas_block.hip", "clover.hip", "force.hip", "hmc.hip", "hmc_driver.cpp", "ops.cpp", "solver.cpp",
+           "scratch.hip", "eigen_vec.hip", "eigen.cpp", "api.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-Wno-unused-command-line-argument", "-Xclang", "-target-feature", "-Xclang",

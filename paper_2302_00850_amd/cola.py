@@ -54,6 +54,19 @@ class CgResult(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+class EigParams(ctypes.Structure):
+    _fields_ = [("system", ctypes.c_int), ("tol", ctypes.c_double),
+                ("inner_reduction", ctypes.c_double), ("inner_max", ctypes.c_int),
+                ("max_sweeps", ctypes.c_int)]
+
+
+class EigResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("sweeps", ctypes.c_int),
+                ("applications", ctypes.c_int),
+                ("eigenvalues", ctypes.POINTER(ctypes.c_double)),
+                ("residuals", ctypes.POINTER(ctypes.c_double)), ("seconds", ctypes.c_double)]
+
+
 class HmcParams(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("eps", ctypes.c_double), ("nsteps", ctypes.c_int),
                 ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int), ("eo", ctypes.c_int),
@@ -87,7 +100,8 @@ EXPORTS = ["cola_abi_version", "cola_create", "cola_destroy", "cola_last_error",
            "cola_reset_stats", "cola_set_tuning", "cola_tune_dump", "cola_gauge_force",
            "cola_gauge_action", "cola_link_update", "cola_momentum_update",
            "cola_hmc_trajectory", "cola_cg_multishift", "cola_fermion_action",
-           "cola_dslash_apply_noalloc"]
+           "cola_dslash_apply_noalloc", "cola_eigensolve", "cola_cg_deflated",
+           "cola_ape_smear", "cola_set_fat_gauge", "cola_tune_load", "cola_tune_save"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -128,9 +142,18 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cola_set_tuning.argtypes = [_vp, ctypes.c_int]
     lib.cola_tune_dump.argtypes = [_vp, ctypes.c_char_p, ctypes.c_size_t]
     lib.cola_tune_dump.restype = ctypes.c_size_t
+    lib.cola_tune_load.argtypes = [_vp, ctypes.c_char_p]
+    lib.cola_tune_save.argtypes = [_vp, ctypes.c_char_p]
     lib.cola_cg_multishift.argtypes = [_vp, _vp, _vp, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(CgParams),
                                        ctypes.POINTER(CgResult), _vp]
+    lib.cola_eigensolve.argtypes = [_vp, _vp, ctypes.c_int, ctypes.POINTER(EigParams),
+                                    ctypes.POINTER(EigResult), _vp]
+    lib.cola_cg_deflated.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                     ctypes.POINTER(CgParams), ctypes.POINTER(CgResult), _vp]
+    lib.cola_ape_smear.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _vp]
+    lib.cola_set_fat_gauge.argtypes = [_vp, _vp, _vp]
     lib.cola_gauge_force.argtypes = [_vp, _vp, _vp, ctypes.c_double, _vp]
     lib.cola_gauge_action.argtypes = [_vp, _vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                       _vp]
@@ -227,6 +250,25 @@ def cola_cg_multishift(h, x, b, nshift, shifts, params: CgParams, result: CgResu
                                                ctypes.byref(result), stream))
 
 
+def cola_eigensolve(h, X, n, params: EigParams, result: EigResult, stream=None):
+    return _check(h, load().cola_eigensolve(h, X, n, ctypes.byref(params), ctypes.byref(result),
+                                            stream))
+
+
+def cola_cg_deflated(h, x, b, nrhs, X, lam, n, params: CgParams, result: CgResult, stream=None):
+    lam_arr = (ctypes.c_double * n)(*lam)
+    return _check(h, load().cola_cg_deflated(h, x, b, nrhs, X, lam_arr, n, ctypes.byref(params),
+                                             ctypes.byref(result), stream))
+
+
+def cola_ape_smear(h, F, U, alpha, nsweeps, stream=None):
+    return _check(h, load().cola_ape_smear(h, F, U, alpha, nsweeps, stream))
+
+
+def cola_set_fat_gauge(h, F, stream=None):
+    return _check(h, load().cola_set_fat_gauge(h, F, stream))
+
+
 def cola_gauge_force(h, F, U, beta, stream=None):
     return _check(h, load().cola_gauge_force(h, F, U, float(beta), stream))
 
@@ -262,6 +304,14 @@ def cola_reset_stats(h):
 
 def cola_set_tuning(h, mode):
     return _check(h, load().cola_set_tuning(h, mode))
+
+
+def cola_tune_load(h, path=None) -> int:
+    return _check(h, load().cola_tune_load(h, path.encode() if path else None))
+
+
+def cola_tune_save(h, path=None) -> int:
+    return _check(h, load().cola_tune_save(h, path.encode() if path else None))
 
 
 def cola_tune_dump(h) -> str:
@@ -383,6 +433,50 @@ class Lattice:
                 "seconds": r.seconds}
         return x, info
 
+    def _nvec(self, X: torch.Tensor) -> int:
+        """Validate a stack of canonical spinors (1 .. 32 of them)."""
+        if X.dtype != torch.complex128 or not X.is_cuda:
+            raise ValueError("vectors must be a complex128 device tensor")
+        shape = tuple(X.shape)
+        if len(shape) == 7 and shape[1:] == self.site_shape + (4, 3) and 1 <= shape[0] <= 32:
+            return shape[0]
+        raise ValueError(f"vector stack shape {shape} is not (n,)+{self.site_shape}+(4,3)")
+
+    def eigensolve(self, X0: torch.Tensor, system=COLA_SYS_SCHUR, tol=1e-8,
+                   inner_reduction=0.1, inner_max=50, max_sweeps=100):
+        """The len(X0) lowest eigenpairs of A (M^H M or S^H S) from the starting vectors
+        X0 (canonical, leading vector axis); returns (eigenvalues, X, info)."""
+        n = self._nvec(X0)
+        X = X0.contiguous().clone()
+        p = EigParams(system, tol, inner_reduction, inner_max, max_sweeps)
+        lam = (ctypes.c_double * n)()
+        res = (ctypes.c_double * n)()
+        r = EigResult(0, 0, 0, ctypes.cast(lam, ctypes.POINTER(ctypes.c_double)),
+                      ctypes.cast(res, ctypes.POINTER(ctypes.c_double)), 0.0)
+        cola_eigensolve(self.h, _ptr(X), n, p, r, _stream())
+        return list(lam), X, {"status": r.status, "sweeps": r.sweeps,
+                              "applications": r.applications, "residuals": list(res),
+                              "seconds": r.seconds}
+
+    def cg_deflated(self, b: torch.Tensor, X: torch.Tensor, lam, system=COLA_SYS_SCHUR,
+                    scheme=COLA_CG_FP64, tol=1e-10, max_iter=20000, reliable_interval=50,
+                    inner_tol=0.0, check_interval=0, block=0):
+        """cg() started from the low-mode part of the solution (eigenpairs X, lam of the
+        same system's A)."""
+        nrhs = self._spinor_rhs(b)
+        n = self._nvec(X)
+        x = torch.zeros_like(b)
+        p = CgParams(system, scheme, block, tol, max_iter, reliable_interval, inner_tol, 1,
+                     check_interval)
+        res = (ctypes.c_double * nrhs)()
+        r = CgResult(0, 0, 0, 0, ctypes.cast(res, ctypes.POINTER(ctypes.c_double)), 0.0)
+        Xc = X.contiguous()
+        cola_cg_deflated(self.h, _ptr(x), _ptr(b.contiguous()), nrhs, _ptr(Xc), list(lam), n, p,
+                         r, _stream())
+        return x, {"status": r.status, "iterations": r.iterations,
+                   "outer_cycles": r.outer_cycles, "true_rel_residual": list(res),
+                   "seconds": r.seconds}
+
     def cg_multishift(self, b: torch.Tensor, shifts, system=COLA_SYS_MDAGM, tol=1e-10,
                       max_iter=20000):
         """(A + shifts[q]) x_q = b for every shift from one Krylov space (FP64); returns
@@ -412,6 +506,19 @@ class Lattice:
         if A.dtype != torch.complex128 or tuple(A.shape) != self.site_shape + (4, 3, 3) \
                 or not A.is_contiguous() or not A.is_cuda:
             raise ValueError(f"{name} must be contiguous complex128 (Lt,Lz,Ly,Lx,4,3,3) on the GPU")
+
+    def ape_smear(self, U: torch.Tensor, alpha: float, nsweeps: int) -> torch.Tensor:
+        """APE-smeared copy of U (nsweeps sweeps of weight alpha, SU(3)-projected)."""
+        self._gauge_like(U, "U")
+        F = torch.empty_like(U)
+        cola_ape_smear(self.h, _ptr(F), _ptr(U.contiguous()), float(alpha), int(nsweeps),
+                       _stream())
+        return F
+
+    def set_fat_gauge(self, F: torch.Tensor):
+        """Switch to the FLIC operator with smeared links F (thin links from set_gauge)."""
+        self._gauge_like(F, "F")
+        cola_set_fat_gauge(self.h, _ptr(F.contiguous()), _stream())
 
     def gauge_force(self, U: torch.Tensor, beta: float) -> torch.Tensor:
         self._gauge_like(U, "U")

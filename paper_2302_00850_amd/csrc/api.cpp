@@ -37,6 +37,8 @@ int check_rhs(cola_handle_t *h, int nrhs) {
 void free_all(cola_handle_t *h) {
     for (auto &g : h->gauge)
         if (g) hipFree(g), g = nullptr;
+    for (auto &g : h->fat)
+        if (g) hipFree(g), g = nullptr;
     for (void **p : {&h->clov64, &h->clovinv64, &h->clov32, &h->clovinv32})
         if (*p) hipFree(*p), *p = nullptr;
     for (auto &kv : h->cache.bufs) hipFree(kv.second.first);
@@ -90,6 +92,15 @@ int cola_create(cola_handle_t **hp, const int dims[4], double kappa, const doubl
     hipError_t e = hipGetDevice(&h->device);
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+    if (e == hipSuccess) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, h->device);
+        if (e == hipSuccess) {
+            h->arch = prop.gcnArchName;
+            const size_t colon = h->arch.find(':');  // drop feature flags
+            if (colon != std::string::npos) h->arch.resize(colon);
+        }
+    }
     if (e == hipSuccess) e = hipMalloc(&h->partial, sizeof(double) * kRedPartialDoubles);
     if (e == hipSuccess) e = hipMalloc(&h->counter, sizeof(unsigned) * kRedCounters);
     if (e == hipSuccess) e = hipMemset(h->counter, 0, sizeof(unsigned) * kRedCounters);
@@ -125,17 +136,16 @@ int cola_destroy(cola_handle_t *h) {
 
 const char *cola_last_error(const cola_handle_t *h) { return h ? h->err.c_str() : "null handle"; }
 
-int cola_set_gauge(cola_handle_t *h, const void *U, void *stream) {
-    if (!h) return COLA_EINVAL;
-    if (!U) return set_error(h, COLA_EINVAL, "null gauge pointer");
-    hipStream_t st = as_stream(stream);
+// Pack a canonical field into the four link formats of dst (allocated on first use);
+// *dev receives the largest SU(3) deviation of its links.
+int pack_links(cola_handle_t *h, const void *U, void *dst[4], double *dev_out, hipStream_t st) {
     const Geom &g = h->g;
     for (int f = 0; f < 4; ++f) {
         const size_t bytes =
             (size_t)2 * 4 * link_chunks((LinkFmt)f) * link_chunk_bytes((LinkFmt)f) * g.S;
-        if (!h->gauge[f]) {
-            COLA_HIP(h, hipMalloc(&h->gauge[f], bytes));
-            COLA_HIP(h, hipMemset(h->gauge[f], 0, bytes));
+        if (!dst[f]) {
+            COLA_HIP(h, hipMalloc(&dst[f], bytes));
+            COLA_HIP(h, hipMemset(dst[f], 0, bytes));
         }
     }
     unsigned long long *dev;
@@ -143,37 +153,104 @@ int cola_set_gauge(cola_handle_t *h, const void *U, void *stream) {
     COLA_TRY(get_vec(h, "su3_dev", 64, &tmp));
     dev = (unsigned long long *)tmp;
     COLA_HIP(h, hipMemsetAsync(dev, 0, 8, st));
-    COLA_HIP(h, launch_pack_gauge(g, U, h->gauge[0], h->gauge[1], h->gauge[2], h->gauge[3], dev, st));
+    COLA_HIP(h, launch_pack_gauge(g, U, dst[0], dst[1], dst[2], dst[3], dev, st));
     unsigned long long bits = 0;
     COLA_HIP(h, hipMemcpyAsync(&bits, dev, 8, hipMemcpyDeviceToHost, st));
     COLA_HIP(h, hipStreamSynchronize(st));
+    memcpy(dev_out, &bits, 8);
+    return COLA_OK;
+}
+
+// The clover blocks A = 1 - kappa csw sum sigma F[W] and A^-1 from the canonical field W.
+int build_clover(cola_handle_t *h, const void *W, hipStream_t st) {
+    const Geom &g = h->g;
+    const size_t cb = (size_t)2 * 36 * g.S;
+    for (void **p : {&h->clov64, &h->clovinv64}) {
+        if (!*p) COLA_HIP(h, hipMalloc(p, cb * 16));
+    }
+    for (void **p : {&h->clov32, &h->clovinv32}) {
+        if (!*p) COLA_HIP(h, hipMalloc(p, cb * 8));
+    }
+    void *badp;
+    COLA_TRY(get_vec(h, "clover_bad", 64, &badp));
+    COLA_HIP(h, hipMemsetAsync(badp, 0, 4, st));
+    COLA_HIP(h, launch_clover_build(g, W, h->kappa, h->csw, h->clov64, h->clovinv64, h->clov32,
+                                    h->clovinv32, (int *)badp, st));
+    int bad = 0;
+    COLA_HIP(h, hipMemcpyAsync(&bad, badp, 4, hipMemcpyDeviceToHost, st));
+    COLA_HIP(h, hipStreamSynchronize(st));
+    if (bad)
+        return set_error(h, COLA_EINVAL,
+                         std::to_string(bad) + " clover blocks are not positive definite");
+    return COLA_OK;
+}
+
+int cola_set_gauge(cola_handle_t *h, const void *U, void *stream) {
+    if (!h) return COLA_EINVAL;
+    if (!U) return set_error(h, COLA_EINVAL, "null gauge pointer");
+    hipStream_t st = as_stream(stream);
     double d;
-    memcpy(&d, &bits, 8);
+    h->flic = false;
+    COLA_TRY(pack_links(h, U, h->gauge, &d, st));
     h->su3_dev = d;
     h->su3 = d <= 1e-12;
     if (h->csw != 0.0) {
-        const size_t cb = (size_t)2 * 36 * g.S;
-        for (void **p : {&h->clov64, &h->clovinv64}) {
-            if (!*p) COLA_HIP(h, hipMalloc(p, cb * 16));
-        }
-        for (void **p : {&h->clov32, &h->clovinv32}) {
-            if (!*p) COLA_HIP(h, hipMalloc(p, cb * 8));
-        }
-        void *badp;
-        COLA_TRY(get_vec(h, "clover_bad", 64, &badp));
-        COLA_HIP(h, hipMemsetAsync(badp, 0, 4, st));
-        COLA_HIP(h, launch_clover_build(g, U, h->kappa, h->csw, h->clov64, h->clovinv64,
-                                        h->clov32, h->clovinv32, (int *)badp, st));
-        int bad = 0;
-        COLA_HIP(h, hipMemcpyAsync(&bad, badp, 4, hipMemcpyDeviceToHost, st));
-        COLA_HIP(h, hipStreamSynchronize(st));
-        if (bad) {
+        const int rc = build_clover(h, U, st);
+        if (rc != COLA_OK) {
             h->gauge_set = false;
-            return set_error(h, COLA_EINVAL,
-                             std::to_string(bad) + " clover blocks are not positive definite");
+            return rc;
         }
     }
     h->gauge_set = true;
+    return COLA_OK;
+}
+
+int cola_set_fat_gauge(cola_handle_t *h, const void *F, void *stream) {
+    if (!h) return COLA_EINVAL;
+    if (!F) return set_error(h, COLA_EINVAL, "null fat-link pointer");
+    if (!h->gauge_set) return set_error(h, COLA_ESTATE, "set the thin links first");
+    hipStream_t st = as_stream(stream);
+    double d;
+    h->flic = false;
+    COLA_TRY(pack_links(h, F, h->fat, &d, st));
+    if (!(d <= 1e-12))
+        return set_error(h, COLA_EINVAL, "smeared links are not SU(3) (deviation " +
+                                             std::to_string(d) + ")");
+    if (h->csw != 0.0) {
+        const int rc = build_clover(h, F, st);
+        if (rc != COLA_OK) {
+            h->gauge_set = false;
+            return rc;
+        }
+    }
+    h->flic = true;
+    return COLA_OK;
+}
+
+int cola_ape_smear(cola_handle_t *h, void *F, const void *U, double alpha, int nsweeps,
+                   void *stream) {
+    if (!h) return COLA_EINVAL;
+    if (!F || !U) return set_error(h, COLA_EINVAL, "null pointer");
+    if (!std::isfinite(alpha) || nsweeps < 0)
+        return set_error(h, COLA_EINVAL, "need a finite alpha and nsweeps >= 0");
+    hipStream_t st = as_stream(stream);
+    const size_t bytes = (size_t)h->g.Vh * 2 * 4 * 9 * 16;
+    if (nsweeps == 0) {
+        if (F != U) COLA_HIP(h, hipMemcpyAsync(F, U, bytes, hipMemcpyDeviceToDevice, st));
+        return COLA_OK;
+    }
+    void *tmp;
+    COLA_TRY(get_vec(h, "ape_tmp", bytes, &tmp));
+    // sweeps alternate between F and the work field so that the last lands in F; a sweep
+    // never reads the field it writes
+    const void *src = U;
+    for (int k = 0; k < nsweeps; ++k) {
+        void *dst = ((nsweeps - 1 - k) % 2 == 0) ? F : tmp;
+        if (dst == src) dst = dst == F ? tmp : F;  // F aliasing U on the first sweep
+        COLA_HIP(h, launch_ape_sweep(h->g, src, dst, alpha, st));
+        src = dst;
+    }
+    if (src != F) COLA_HIP(h, hipMemcpyAsync(F, src, bytes, hipMemcpyDeviceToDevice, st));
     return COLA_OK;
 }
 
@@ -290,6 +367,43 @@ int cola_cg_multishift(cola_handle_t *h, void *x, const void *b, int nshift, con
     return cg_multishift_impl(h, x, b, nshift, shifts, p, r, as_stream(stream));
 }
 
+int cola_eigensolve(cola_handle_t *h, void *X, int n, const cola_eig_params_t *p,
+                    cola_eig_result_t *r, void *stream) {
+    if (!h) return COLA_EINVAL;
+    if (!X || !p) return set_error(h, COLA_EINVAL, "null pointer");
+    if (n < 1 || n > kEigMax) return set_error(h, COLA_EINVAL, "n must be 1 .. 32");
+    if (p->system != COLA_SYS_MDAGM && p->system != COLA_SYS_SCHUR)
+        return set_error(h, COLA_EINVAL, "the eigensolver runs on the MDAGM and SCHUR systems");
+    if (!(p->tol > 0)) return set_error(h, COLA_EINVAL, "tol must be > 0");
+    if (!h->gauge_set) return set_error(h, COLA_ESTATE, "no gauge field set");
+    return eigensolve_impl(h, X, n, p, r, as_stream(stream));
+}
+
+int cola_cg_deflated(cola_handle_t *h, void *x, const void *b, int nrhs, const void *X,
+                     const double *lambda, int n, const cola_cg_params_t *p,
+                     cola_cg_result_t *r, void *stream) {
+    if (!h) return COLA_EINVAL;
+    if (!x || !b || !X || !lambda || !p) return set_error(h, COLA_EINVAL, "null pointer");
+    if (x == b) return set_error(h, COLA_EINVAL, "x and b must not overlap");
+    COLA_TRY(check_rhs(h, nrhs));
+    if (n < 1 || n > kEigMax) return set_error(h, COLA_EINVAL, "n must be 1 .. 32");
+    for (int i = 0; i < n; ++i)
+        if (!(lambda[i] > 0) || !std::isfinite(lambda[i]))
+            return set_error(h, COLA_EINVAL, "eigenvalues must be finite and > 0");
+    if (p->system != COLA_SYS_MDAGM && p->system != COLA_SYS_SCHUR)
+        return set_error(h, COLA_EINVAL, "deflated CG runs on the MDAGM and SCHUR systems");
+    if (p->scheme < COLA_CG_FP64 || p->scheme > COLA_CG_FP32_DEFECT)
+        return set_error(h, COLA_EINVAL, "unknown scheme");
+    if (!(p->tol > 0) || p->max_iter < 1) return set_error(h, COLA_EINVAL, "bad tol / max_iter");
+    if (p->block && (p->system != COLA_SYS_SCHUR || (p->scheme != COLA_CG_FP16_DEFECT &&
+                                                     p->scheme != COLA_CG_FP32_DEFECT)))
+        return set_error(h, COLA_EINVAL, "block CG needs a DEFECT scheme on the SCHUR system");
+    if (!h->gauge_set) return set_error(h, COLA_ESTATE, "no gauge field set");
+    if (p->scheme != COLA_CG_FP64 && !h->su3)
+        return set_error(h, COLA_EINVAL, "mixed schemes need an SU(3) gauge field");
+    return cg_deflated_impl(h, x, b, nrhs, X, lambda, n, p, r, as_stream(stream));
+}
+
 int cola_fermion_force(cola_handle_t *h, void *F, const void *X, const void *Y, int mode,
                        void *stream) {
     if (!h) return COLA_EINVAL;
@@ -297,6 +411,7 @@ int cola_fermion_force(cola_handle_t *h, void *F, const void *X, const void *Y, 
     if (mode != COLA_FORCE_GRAD && mode != COLA_FORCE_LIE)
         return set_error(h, COLA_EINVAL, "unknown force mode");
     if (h->csw != 0.0) return set_error(h, COLA_EINVAL, "force of the clover term not available");
+    if (h->flic) return set_error(h, COLA_EINVAL, "force of the FLIC operator not available");
     if (!h->gauge_set) return set_error(h, COLA_ESTATE, "no gauge field set");
     COLA_HIP(h, launch_force(h->g, h->gauge[0], X, Y, F, h->kappa, h->phase, mode,
                              as_stream(stream)));
@@ -321,6 +436,16 @@ int cola_set_tuning(cola_handle_t *h, int mode) {
     if (!h || mode < 0 || mode > 2) return COLA_EINVAL;
     h->tune_mode = mode;
     return COLA_OK;
+}
+
+int cola_tune_load(cola_handle_t *h, const char *path) {
+    if (!h) return COLA_EINVAL;
+    return tune_cache_load(h, path);
+}
+
+int cola_tune_save(cola_handle_t *h, const char *path) {
+    if (!h) return COLA_EINVAL;
+    return tune_cache_save(h, path);
 }
 
 size_t cola_tune_dump(const cola_handle_t *h, char *buf, size_t len) {

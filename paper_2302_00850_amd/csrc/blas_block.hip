@@ -130,6 +130,76 @@ __global__ void __launch_bounds__(256) block_xpay_kernel(void *Pn, const void *R
     }
 }
 
+// Z = H^-1 B restricted to the active columns (bit q of act), H Hermitian positive
+// semi-definite, read from a Gram result (transposed layout: H_ab at (b n + a) 2), B the
+// same way; Z row-major complex.  Cholesky H = L L^H over the active indices in order;
+// a pivot below 1e-13 of the largest active diagonal marks a null direction, whose row of
+// Z is zero (this deflates linearly dependent search directions); inactive rows and
+// columns of Z are zero.  One thread: n <= 16, a few thousand flops.
+__global__ void __launch_bounds__(64) block_solve_kernel(const double *Hg, const double *Bg,
+                                                         unsigned act, int n, double *Z) {
+    __shared__ cpx<double> L[kMaxN * kMaxN];
+    __shared__ cpx<double> y[kMaxN];
+    __shared__ int ix[kMaxN];
+    __shared__ int live[kMaxN];
+    if (threadIdx.x != 0) return;
+    auto H = [&](int a, int b) { return cpx<double>{Hg[(b * n + a) * 2], Hg[(b * n + a) * 2 + 1]}; };
+    auto B = [&](int a, int b) { return cpx<double>{Bg[(b * n + a) * 2], Bg[(b * n + a) * 2 + 1]}; };
+    for (int k = 0; k < 2 * n * n; ++k) Z[k] = 0.0;
+    int m = 0;
+    for (int q = 0; q < n; ++q)
+        if (act >> q & 1u) ix[m++] = q;
+    if (m == 0) return;
+    double dmax = 0.0;
+    for (int j = 0; j < m; ++j) dmax = fmax(dmax, H(ix[j], ix[j]).x);
+    for (int k = 0; k < m * m; ++k) L[k] = {0.0, 0.0};
+    for (int j = 0; j < m; ++j) {
+        double d = H(ix[j], ix[j]).x;
+        for (int k = 0; k < j; ++k) d -= norm2(L[j * m + k]);
+        if (!(d > 1e-13 * dmax)) {
+            live[j] = 0;
+            continue;
+        }
+        live[j] = 1;
+        const double ljj = sqrt(d);
+        L[j * m + j] = {ljj, 0.0};
+        for (int i = j + 1; i < m; ++i) {
+            cpx<double> s = H(ix[i], ix[j]);
+            for (int k = 0; k < j; ++k)
+                s = s - cmul(L[i * m + k], cpx<double>{L[j * m + k].x, -L[j * m + k].y});
+            L[i * m + j] = {s.x / ljj, s.y / ljj};
+        }
+    }
+    for (int cj = 0; cj < m; ++cj) {
+        const int col = ix[cj];
+        for (int i = 0; i < m; ++i) {  // L y = b
+            if (!live[i]) {
+                y[i] = {0.0, 0.0};
+                continue;
+            }
+            cpx<double> s = B(ix[i], col);
+            for (int k = 0; k < i; ++k) s = s - cmul(L[i * m + k], y[k]);
+            const double l = L[i * m + i].x;
+            y[i] = {s.x / l, s.y / l};
+        }
+        for (int i = m - 1; i >= 0; --i) {  // L^H z = y
+            if (!live[i]) {
+                y[i] = {0.0, 0.0};
+                continue;
+            }
+            cpx<double> s = y[i];
+            for (int k = i + 1; k < m; ++k)
+                s = s - cmul(cpx<double>{L[k * m + i].x, -L[k * m + i].y}, y[k]);
+            const double l = L[i * m + i].x;
+            y[i] = {s.x / l, s.y / l};
+        }
+        for (int i = 0; i < m; ++i) {
+            Z[2 * (ix[i] * n + col)] = y[i].x;
+            Z[2 * (ix[i] * n + col) + 1] = y[i].y;
+        }
+    }
+}
+
 struct Shape {
     int T, grid;
 };
@@ -175,6 +245,13 @@ hipError_t launch_block_axpy(int S, int n, SpinorFmt fx, SpinorFmt fp, void *X, 
                            R, Q, alpha, S, n);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_block_solve(const double *H, const double *B, unsigned act, int n, double *Z,
+                              hipStream_t st) {
+    if (n < 1 || n > kMaxN) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(block_solve_kernel, dim3(1), dim3(64), 0, st, H, B, act, n, Z);
     return hipGetLastError();
 }
 

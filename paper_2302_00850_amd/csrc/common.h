@@ -82,6 +82,7 @@ struct HopArgs {
     void *out;           // parity `parity` block
     const void *x;       // parity `parity` block (epilogues 1, 3, 4)
     const void *gauge;   // packed gauge buffer of the launch precision
+    const void *gauge_fat;  // FLIC operator: packed smeared links (same format), else null
     const void *clov;    // packed clover buffer (both parities) for epilogues 2-4
     double *partial;     // per-block |out|^2 partials [R][grid] (want_norm)
     uint32_t total;      // (Lt / tchunk) * (Vh / Lt) * groups lanes of work

@@ -814,6 +814,57 @@ __device__ __forceinline__ void clover_apply(const void *clov, int S, int p, uin
     }
 }
 
+// out = C in from a site's clover block staged in LDS: pair m (0..35, as in memory, the
+// second chiral block from m = 18) at c[2m], c[2m + 1].  The same arithmetic, in the same
+// order, as clover_apply.
+constexpr int kClovStage = 76;  // floats per staged site (72 used; the padding spreads banks)
+
+template <typename T>
+__device__ __forceinline__ void clover_apply_lds(const float *c, const cpx<T> in[12],
+                                                 cpx<T> out[12]) {
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+        const float *q = c + 36 * blk;
+        float w[36];
+#pragma unroll
+        for (int k = 0; k < 36; k += 4) {
+            const float4 v = *(const float4 *)(q + k);
+            w[k] = v.x;
+            w[k + 1] = v.y;
+            w[k + 2] = v.z;
+            w[k + 3] = v.w;
+        }
+        T d[6];
+        cpx<T> o[15];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) d[k] = (T)w[k];
+#pragma unroll
+        for (int k = 0; k < 15; ++k) o[k] = {(T)w[6 + 2 * k], (T)w[7 + 2 * k]};
+        const cpx<T> *v = in + 6 * blk;
+        cpx<T> *y = out + 6 * blk;
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            cpx<T> s = scale(d[r], v[r]);
+#pragma unroll
+            for (int cc = 0; cc < 6; ++cc) {
+                if (cc < r) s = cmadd(s, o[r * (r - 1) / 2 + cc], v[cc]);
+                if (cc > r) s = cjmadd(s, o[cc * (cc - 1) / 2 + r], v[cc]);
+            }
+            y[r] = s;
+        }
+    }
+}
+
+// Stage pair m of the FP32 clover block of site i (parity p) into c[2m], c[2m + 1].
+__device__ __forceinline__ void stage_clover_pair(const void *clov, int S, int p, uint32_t i,
+                                                  int m, float *c) {
+    struct pair { float a, b; };
+    const pair *base = (const pair *)clov + (size_t)(p * 36 + m) * S;
+    const pair v = bload<pair, kCpolNT>(buf(base, (uint32_t)S * sizeof(pair)), i * 8u);
+    c[2 * m] = v.a;
+    c[2 * m + 1] = v.b;
+}
+
 // ---------------------------------------------------------------- reduction
 
 // Per-block part of a two-kernel reduction: the lanes' values v[0..n) for columns q0..

@@ -16,6 +16,7 @@ namespace cola {
 
 constexpr int kMaxRhs = kRedMaxWidth;
 constexpr int kMaxGrid = kRedMaxBlocks;
+constexpr int kEigMax = 32;  // eigenpairs of one cola_eigensolve call
 // size of the fixed device workspace of cola_dslash_apply_noalloc (per device)
 constexpr size_t kScratchBytes = (size_t)128 << 20;
 
@@ -46,6 +47,7 @@ struct cola_handle {
     unsigned flags = 0;
     int device = 0;
     int num_cu = 0;  // compute units of the device
+    std::string arch;  // the device's architecture name (tuned shapes are kept per device)
     std::map<std::string, int> occupancy;  // resident blocks per CU by launch variant
 
     // packed gauge fields by cola::LinkFmt
@@ -53,6 +55,10 @@ struct cola_handle {
     bool gauge_set = false;
     bool su3 = false;
     double su3_dev = 0;
+    // FLIC operator: the smeared ("fat") links in the packed formats of `gauge`; flic is
+    // set by cola_set_fat_gauge and cleared by cola_set_gauge
+    void *fat[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool flic = false;
     // clover blocks (both parities): A and A^-1, FP64 and FP32
     void *clov64 = nullptr, *clovinv64 = nullptr, *clov32 = nullptr, *clovinv32 = nullptr;
 
@@ -149,6 +155,13 @@ int apply_op(cola_handle_t *h, void *out, const void *in, int op, int parity, in
              hipStream_t st, double *norm_result = nullptr, char *ws = nullptr);
 size_t op_workspace_bytes(const cola_handle_t *h, int op, int prec, int nrhs);
 
+// low-eigenmode solver and deflated CG (eigen.cpp)
+int eigensolve_impl(cola_handle_t *h, void *X, int n, const cola_eig_params_t *p,
+                    cola_eig_result_t *r, hipStream_t st);
+int cg_deflated_impl(cola_handle_t *h, void *x, const void *b, int nrhs, const void *X,
+                     const double *lambda, int n, const cola_cg_params_t *p, cola_cg_result_t *r,
+                     hipStream_t st);
+
 // device address of this handle's device's fixed workspace (kScratchBytes)
 int scratch_address(cola_handle_t *h, void **out);
 
@@ -156,5 +169,9 @@ int scratch_address(cola_handle_t *h, void **out);
 int flush_timing(cola_handle_t *h, bool wait_all);
 
 std::string tune_key(const cola_handle_t *h, int prec, int nrhs, int epi, int norm);
+// the process-wide table of tuned launch shapes and its file (path null: the default
+// file); return the number of entries read / written, or < 0
+int tune_cache_load(cola_handle_t *h, const char *path);
+int tune_cache_save(cola_handle_t *h, const char *path);
 
 }  // namespace cola

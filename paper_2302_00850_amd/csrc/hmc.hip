@@ -225,13 +225,155 @@ __device__ __forceinline__ M3 expi3(const M3 &P, double eps) {
     return E;
 }
 
+// Rows re-orthonormalised (Gram-Schmidt on rows 0 and 1, row 2 = conj(row0 x row1)): the
+// SU(3) matrix nearest to a link that rounding has moved off the group by O(1e-16).
+__device__ __forceinline__ M3 reunitarise(M3 m) {
+    double n0 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) n0 += norm2(m.a[0][j]);
+    const double i0 = 1.0 / sqrt(n0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m.a[0][j] = {i0 * m.a[0][j].x, i0 * m.a[0][j].y};
+    C d = {0.0, 0.0};  // <row0, row1>
+#pragma unroll
+    for (int j = 0; j < 3; ++j) d = cmadd(d, conj(m.a[0][j]), m.a[1][j]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m.a[1][j] = m.a[1][j] - cmul(d, m.a[0][j]);
+    double n1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) n1 += norm2(m.a[1][j]);
+    const double i1 = 1.0 / sqrt(n1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m.a[1][j] = {i1 * m.a[1][j].x, i1 * m.a[1][j].y};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+        const C c = cmul(m.a[0][k1], m.a[1][k2]) - cmul(m.a[0][k2], m.a[1][k1]);
+        m.a[2][k] = conj(c);
+    }
+    return m;
+}
+
+// U <- exp(i eps P) U, re-unitarised: without the projection, rounding moves the links
+// off SU(3) by about 1e-16 per update, which over many trajectories would exceed the
+// SU(3) check that the compressed (12-real) link formats require.
 __global__ void __launch_bounds__(256) link_update_kernel(C *__restrict__ U,
                                                           const C *__restrict__ P, double eps,
                                                           size_t nlinks) {
     for (size_t l = (size_t)blockIdx.x * blockDim.x + threadIdx.x; l < nlinks;
          l += (size_t)gridDim.x * blockDim.x) {
         const M3 E = expi3(ld3(P + l * 9), eps);
-        st3(U + l * 9, mm(E, ld3(U + l * 9)));
+        st3(U + l * 9, reunitarise(mm(E, ld3(U + l * 9))));
+    }
+}
+
+// ---------------------------------------------------------------- APE smearing
+// (the smeared links of the fat-link irrelevant clover operator)
+
+__device__ __forceinline__ C cdiv(C a, C b) {
+    const double d = 1.0 / (b.x * b.x + b.y * b.y);
+    return {(a.x * b.x + a.y * b.y) * d, (a.y * b.x - a.x * b.y) * d};
+}
+
+__device__ __forceinline__ C det3(const M3 &m) {
+    const C c0 = cmul(m.a[1][1], m.a[2][2]) - cmul(m.a[1][2], m.a[2][1]);
+    const C c1 = cmul(m.a[1][2], m.a[2][0]) - cmul(m.a[1][0], m.a[2][2]);
+    const C c2 = cmul(m.a[1][0], m.a[2][1]) - cmul(m.a[1][1], m.a[2][0]);
+    return cmadd(cmadd(cmul(m.a[0][0], c0), m.a[0][1], c1), m.a[0][2], c2);
+}
+
+// X^{-H} = adj(X)^H / conj(det X), adj the adjugate (transposed cofactors)
+__device__ __forceinline__ M3 inv_dag(const M3 &X, C det) {
+    M3 cof;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            cof.a[i][j] = cmul(X.a[i1][j1], X.a[i2][j2]) - cmul(X.a[i1][j2], X.a[i2][j1]);
+        }
+    // (adj X)^H = conj(cof); divided by conj(det)
+    M3 r;
+    const C cd = conj(det);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) r.a[i][j] = cdiv(conj(cof.a[i][j]), cd);
+    return r;
+}
+
+// The SU(3) matrix nearest to V: the unitary polar factor W (V = W H, H Hermitian
+// positive) by Newton's iteration X <- (g X + X^{-H} / g) / 2 with the determinant scaling
+// g = |det X|^{-1/3} (quadratic convergence; stopped when an iteration changes no entry
+// by more than 1e-15), then det(W)^{-1/3} with the principal cube root.
+__device__ M3 project_su3(const M3 &V) {
+    M3 X = V;
+    for (int it = 0; it < 40; ++it) {
+        const C det = det3(X);
+        const double g = pow(sqrt(det.x * det.x + det.y * det.y), -1.0 / 3.0);
+        const M3 Y = inv_dag(X, det);
+        double change = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const C n = {0.5 * (g * X.a[i][j].x + Y.a[i][j].x / g),
+                             0.5 * (g * X.a[i][j].y + Y.a[i][j].y / g)};
+                change = fmax(change, fmax(fabs(n.x - X.a[i][j].x), fabs(n.y - X.a[i][j].y)));
+                X.a[i][j] = n;
+            }
+        if (change <= 1e-15) break;
+    }
+    const C d = det3(X);
+    const double th = atan2(d.y, d.x) / 3.0;
+    const C ph = {cos(th), -sin(th)};  // det^{-1/3}
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) X.a[i][j] = cmul(X.a[i][j], ph);
+    return X;
+}
+
+// One APE sweep: V_mu(x) = (1 - alpha) U_mu(x) + (alpha / 6) sum over nu != mu of the
+// staples U_nu(x) U_mu(x+nu) U_nu(x+mu)^H and U_nu(x-nu)^H U_mu(x-nu) U_nu(x-nu+mu), then
+// projected to SU(3).  Periodic links; reads U, writes Out (no aliasing).
+__global__ void __launch_bounds__(256) ape_kernel(const Geom g, const C *__restrict__ U,
+                                                  C *__restrict__ Out, double alpha) {
+    const uint32_t V = 2u * (uint32_t)g.Vh;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < 4u * V;
+         t += gridDim.x * blockDim.x) {
+        const uint32_t s = t >> 2;
+        const int mu = (int)(t & 3u);
+        int x[4], y[4], w[4], z[4];
+        coords(g, s, x);
+        const uint32_t sp = step(g, x, mu, 1, y);  // x + mu
+        M3 S;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) S.a[i][j] = C{0.0, 0.0};
+        for (int nu = 0; nu < 4; ++nu) {
+            if (nu == mu) continue;
+            const uint32_t sn = step(g, x, nu, 1, w);    // x + nu
+            const uint32_t sm = step(g, x, nu, -1, w);   // x - nu
+            const uint32_t smp = step(g, w, mu, 1, z);   // x - nu + mu
+            const M3 up = mmd(mm(ld3(link(U, s, nu)), ld3(link(U, sn, mu))), ld3(link(U, sp, nu)));
+            const M3 lo = mm(mdm(ld3(link(U, sm, nu)), ld3(link(U, sm, mu))), ld3(link(U, smp, nu)));
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) S.a[i][j] = S.a[i][j] + up.a[i][j] + lo.a[i][j];
+        }
+        const M3 Um = ld3(link(U, s, mu));
+        M3 Vm;
+        const double a0 = 1.0 - alpha, a1 = alpha / 6.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                Vm.a[i][j] = {fma(a1, S.a[i][j].x, a0 * Um.a[i][j].x),
+                              fma(a1, S.a[i][j].y, a0 * Um.a[i][j].y)};
+        st3(Out + (size_t)t * 9, project_su3(Vm));
     }
 }
 
@@ -316,6 +458,14 @@ hipError_t launch_link_update(void *U, const void *P, double eps, size_t nlinks,
                               hipStream_t st) {
     hipLaunchKernelGGL(link_update_kernel, dim3(grid_for(nlinks)), dim3(256), 0, st, (C *)U,
                        (const C *)P, eps, nlinks);
+    return hipGetLastError();
+}
+
+hipError_t launch_ape_sweep(const Geom &g, const void *U, void *Out, double alpha,
+                            hipStream_t st) {
+    const size_t n = (size_t)8 * g.Vh;
+    hipLaunchKernelGGL(ape_kernel, dim3(grid_for(n)), dim3(256), 0, st, g, (const C *)U, (C *)Out,
+                       alpha);
     return hipGetLastError();
 }
 

@@ -236,6 +236,10 @@ int cola_hmc_trajectory(cola_handle_t *h, void *U, void *P, const void *phi,
         return set_error(h, COLA_EINVAL, "need nsteps >= 1, finite eps > 0 and finite beta");
     if (phi && h->csw != 0.0)
         return set_error(h, COLA_EINVAL, "fermion force of the clover term not available");
+    if (h->flic)
+        return set_error(h, COLA_EINVAL,
+                         "the trajectory driver runs the Wilson operator (the FLIC force, "
+                         "through the smearing, is not built)");
     if (phi && (!(p->cg_tol > 0.0) || p->cg_max_iter < 1))
         return set_error(h, COLA_EINVAL, "need cg_tol > 0 and cg_max_iter >= 1");
     if (phi && (p->cg_scheme < COLA_CG_FP64 || p->cg_scheme > COLA_CG_FP32_DEFECT))

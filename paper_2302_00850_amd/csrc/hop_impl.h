@@ -21,6 +21,14 @@
 //                  (or C x + a D in) in place of storing o
 // and |out|^2 per rhs can be accumulated: per-block partials, summed in block
 // order by a reduce_partials launch that follows.
+//
+// FL (the fat-link irrelevant clover operator): the hop of direction mu is
+// (F - g_mu U) psi(x+mu) forward and (F^H + g_mu U^H) psi(x-mu) backward, with U the
+// thin links (a.gauge) and F the smeared links (a.gauge_fat).  Writing
+// 1 = (1 + g)/2 + (1 - g)/2, the term of the projector (1 + s g_mu) (s = +-1) carries
+// the link F + s sg U, where (1 + sg g_mu) is the Wilson projector of that direction
+// (the same sign conventions, dagger included), so each direction costs two spin
+// projections and four SU(3) products of the combined links F +- U.
 #pragma once
 
 #include <type_traits>
@@ -67,7 +75,7 @@ __device__ __forceinline__ void hop_fetch(const HopArgs &a, const SpinorBlock<SF
 // lane's RPT right-hand sides at checkerboard site i (coordinates x), from the fetched
 // neighbour spinor.  A template, so the eight directions are unrolled by construction
 // and every spin-projection branch resolves at compile time.
-template <int MU, int DIR, SpinorFmt SF, LinkFmt LF, int RPT, bool RPH, bool SHL>
+template <int MU, int DIR, SpinorFmt SF, LinkFmt LF, int RPT, bool RPH, bool SHL, bool FL>
 __device__ __forceinline__ void hop_dir(const HopArgs &a, int p, uint32_t i, const int x[4],
                                         typename SpinorT<SF>::real sg_f,
                                         cpx<typename SpinorT<SF>::real> acc[RPT][12],
@@ -90,7 +98,45 @@ __device__ __forceinline__ void hop_dir(const HopArgs &a, int p, uint32_t i, con
         const T im = dir == 0 ? (T)a.phase[mu].y : -(T)a.phase[mu].y;
         ph = bnd ? C{(T)a.phase[mu].x, im} : C{(T)1, (T)0};
     }
-    if constexpr (SF == SpinorFmt::F16) {
+    if constexpr (FL) {
+        static_assert(SF != SpinorFmt::F16 && !SHL, "FLIC hops: FP64 / FP32, per-lane links");
+        C u[3][3], fl[3][3];
+        const int lpar = dir == 0 ? p : 1 - p;
+        const uint32_t li = dir == 0 ? i : n;
+        load_link<LF, T>(a.gauge, g.S, lpar, mu, li, u);
+        load_link<LF, T>(a.gauge_fat, g.S, lpar, mu, li, fl);
+        // in place: fl = F + U (with the projector 1 + sg g_mu), u = F - U (1 - sg g_mu)
+#pragma unroll
+        for (int r0 = 0; r0 < 3; ++r0)
+#pragma unroll
+            for (int c0 = 0; c0 < 3; ++c0) {
+                const C f0 = fl[r0][c0];
+                fl[r0][c0] = f0 + u[r0][c0];
+                u[r0][c0] = f0 - u[r0][c0];
+            }
+        const T half = (T)0.5 * eta;
+        auto term = [&](const C (&L)[3][3], T sp) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                C h[6], w[6];
+                project(mu, sp, f.s[r], h);
+                if constexpr (dir == 0) {
+                    su3_mul(L, h, w);
+                    su3_mul(L, h + 3, w + 3);
+                } else {
+                    su3_dag_mul(L, h, w);
+                    su3_dag_mul(L, h + 3, w + 3);
+                }
+                if constexpr (!RPH) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) w[k] = cmul(ph, w[k]);
+                }
+                expand_add(mu, sp, w, acc[r], half);
+            }
+        };
+        term(fl, sg);
+        term(u, -sg);
+    } else if constexpr (SF == SpinorFmt::F16) {
         // packed-half projection and dot2 products: FP16 x FP16 products are exact
         // and summed in FP32; the per-site scale rides on eta.  The link operands are
         // prepared once for the lane's RPT right-hand sides, which are adjacent in
@@ -149,13 +195,19 @@ __device__ __forceinline__ void hop_dir(const HopArgs &a, int p, uint32_t i, con
         for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(acc[r][c].x), "+v"(acc[r][c].y));
 }
 
-template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, int EPI, bool RPH, bool SHL>
+template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, int EPI, bool RPH, bool SHL,
+          bool FL = false>
 __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     using T = typename SpinorT<SF>::real;
     using C = cpx<T>;
     extern __shared__ double red[];
-    // SHL: the site's eight links staged in LDS by its first eight lanes
+    // SHL: the site's eight links staged in LDS by its first eight lanes, and with a clover
+    // epilogue (FP32 blocks) the site's clover block by all its lanes
+    constexpr bool CLV = EPI == EPI_CLOV || EPI == EPI_CLOV_XPAY || EPI == EPI_XPAY_CLOV ||
+                         EPI == EPI_CLOV_XPAY_CG;
+    constexpr bool SCL = SHL && CLV && std::is_same<CR, float>::value;
     __shared__ __attribute__((aligned(16))) uint32_t stage[SHL ? kStageSites * kStageSite : 4];
+    __shared__ __attribute__((aligned(16))) float cstage[SCL ? kStageSites * kClovStage : 4];
     const Geom &g = a.g;
     const int p = a.parity;
     const SpinorBlock<SF, true> in(a.in, g.S, a.nrhs);
@@ -209,6 +261,8 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
         int x[4];
         site_coords(g, i, p, x);
         const uint32_t *staged = nullptr;
+        const float *cstaged = nullptr;
+        (void)cstaged;
         if constexpr (SHL) {
             // block = sites_per_block sites x groups lanes, whole sites; lane j stages links
             // j, j + groups, ... (link d: mu = d / 2, backward for odd d)
@@ -219,6 +273,12 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
                 const int mu = (int)(d >> 1);
                 const uint32_t n = nb_bwd_rt(g, i, x, mu);
                 stage_link<LF>(a.gauge, g.S, p, mu, (d & 1) != 0, i, n, mine + d * kStageWords);
+            }
+            if constexpr (SCL) {
+                float *cm = cstage + slot * kClovStage;
+                for (uint32_t m = j; valid && m < 36; m += (uint32_t)a.groups)
+                    stage_clover_pair(a.clov, g.S, p, i, (int)m, cm);
+                cstaged = cm;
             }
             __syncthreads();
             staged = mine;
@@ -234,20 +294,20 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
         Fetched<SF, RPT> fa, fb;
         hop_fetch<0, 0, SF, RPT>(a, in, i, x, j, fa);
         hop_fetch<0, 1, SF, RPT>(a, in, i, x, j, fb);
-        hop_dir<0, 0, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fa);
+        hop_dir<0, 0, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fa);
         hop_fetch<1, 0, SF, RPT>(a, in, i, x, j, fa);
-        hop_dir<0, 1, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fb);
+        hop_dir<0, 1, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fb);
         hop_fetch<1, 1, SF, RPT>(a, in, i, x, j, fb);
-        hop_dir<1, 0, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fa);
+        hop_dir<1, 0, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fa);
         hop_fetch<2, 0, SF, RPT>(a, in, i, x, j, fa);
-        hop_dir<1, 1, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fb);
+        hop_dir<1, 1, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fb);
         hop_fetch<2, 1, SF, RPT>(a, in, i, x, j, fb);
-        hop_dir<2, 0, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fa);
+        hop_dir<2, 0, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fa);
         hop_fetch<3, 0, SF, RPT>(a, in, i, x, j, fa);
-        hop_dir<2, 1, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fb);
+        hop_dir<2, 1, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fb);
         hop_fetch<3, 1, SF, RPT>(a, in, i, x, j, fb);
-        hop_dir<3, 0, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fa);
-        hop_dir<3, 1, SF, LF, RPT, RPH, SHL>(a, p, i, x, sg_f, acc, staged, fb);
+        hop_dir<3, 0, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fa);
+        hop_dir<3, 1, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fb);
 
         const T ca = (T)a.a;
         constexpr bool CG = EPI == EPI_XPAY_CG || EPI == EPI_CLOV_XPAY_CG;
@@ -264,11 +324,17 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
                 C d[12];
 #pragma unroll
                 for (int c = 0; c < 12; ++c) d[c] = o[c];
-                clover_apply<CR, T>(a.clov, g.S, p, i, d, o);
+                if constexpr (SCL)
+                    clover_apply_lds<T>(cstaged, d, o);
+                else
+                    clover_apply<CR, T>(a.clov, g.S, p, i, d, o);
             } else if constexpr (EPI == EPI_CLOV_XPAY || EPI == EPI_CLOV_XPAY_CG) {
                 C xv[12], cx[12];
                 xin.load(i, rr, xv);
-                clover_apply<CR, T>(a.clov, g.S, p, i, xv, cx);
+                if constexpr (SCL)
+                    clover_apply_lds<T>(cstaged, xv, cx);
+                else
+                    clover_apply<CR, T>(a.clov, g.S, p, i, xv, cx);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) o[c] = add_s(cx[c], ca, o[c]);
             } else if constexpr (EPI == EPI_XPAY_CLOV) {
@@ -276,7 +342,10 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
                 xin.load(i, rr, xv);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) xv[c] = add_s(xv[c], ca, o[c]);
-                clover_apply<CR, T>(a.clov, g.S, p, i, xv, o);
+                if constexpr (SCL)
+                    clover_apply_lds<T>(cstaged, xv, o);
+                else
+                    clover_apply<CR, T>(a.clov, g.S, p, i, xv, o);
             }
             if constexpr (CG) {
                 // x += alpha p, r -= alpha o; o becomes the stored r (for the norm)
@@ -325,33 +394,50 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     }
 }
 
-template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, int EPI, bool RPH, bool SHL>
+template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, int EPI, bool RPH, bool SHL,
+          bool FL = false>
 hipError_t hop_launch_t(const HopArgs &a, int grid, int block, hipStream_t st) {
     const size_t shm = a.want_norm ? (size_t)a.sites_per_block * a.nrhs * sizeof(double) : 0;
     if (a.occupancy)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            a.occupancy, hop_kernel<SF, LF, CR, RPT, EPI, RPH, SHL>, block, shm);
-    hipLaunchKernelGGL((hop_kernel<SF, LF, CR, RPT, EPI, RPH, SHL>), dim3(grid), dim3(block), shm,
-                       st, a);
+            a.occupancy, hop_kernel<SF, LF, CR, RPT, EPI, RPH, SHL, FL>, block, shm);
+    hipLaunchKernelGGL((hop_kernel<SF, LF, CR, RPT, EPI, RPH, SHL, FL>), dim3(grid), dim3(block),
+                       shm, st, a);
     return hipGetLastError();
 }
 
-template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, bool RPH, bool SHL = false>
+template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, bool RPH, bool SHL = false,
+          bool FL = false>
 hipError_t hop_launch_epi(const HopArgs &a, int grid, int block, hipStream_t st) {
     switch (a.epi) {
-        case EPI_NONE: return hop_launch_t<SF, LF, CR, RPT, EPI_NONE, RPH, SHL>(a, grid, block, st);
-        case EPI_XPAY: return hop_launch_t<SF, LF, CR, RPT, EPI_XPAY, RPH, SHL>(a, grid, block, st);
-        case EPI_CLOV: return hop_launch_t<SF, LF, CR, RPT, EPI_CLOV, RPH, SHL>(a, grid, block, st);
+        case EPI_NONE:
+            return hop_launch_t<SF, LF, CR, RPT, EPI_NONE, RPH, SHL, FL>(a, grid, block, st);
+        case EPI_XPAY:
+            return hop_launch_t<SF, LF, CR, RPT, EPI_XPAY, RPH, SHL, FL>(a, grid, block, st);
+        case EPI_CLOV:
+            return hop_launch_t<SF, LF, CR, RPT, EPI_CLOV, RPH, SHL, FL>(a, grid, block, st);
         case EPI_CLOV_XPAY:
-            return hop_launch_t<SF, LF, CR, RPT, EPI_CLOV_XPAY, RPH, SHL>(a, grid, block, st);
+            return hop_launch_t<SF, LF, CR, RPT, EPI_CLOV_XPAY, RPH, SHL, FL>(a, grid, block, st);
         case EPI_XPAY_CLOV:
-            return hop_launch_t<SF, LF, CR, RPT, EPI_XPAY_CLOV, RPH, SHL>(a, grid, block, st);
+            return hop_launch_t<SF, LF, CR, RPT, EPI_XPAY_CLOV, RPH, SHL, FL>(a, grid, block, st);
         case EPI_XPAY_CG:
-            return hop_launch_t<SF, LF, CR, RPT, EPI_XPAY_CG, RPH, SHL>(a, grid, block, st);
+            return hop_launch_t<SF, LF, CR, RPT, EPI_XPAY_CG, RPH, SHL, FL>(a, grid, block, st);
         case EPI_CLOV_XPAY_CG:
-            return hop_launch_t<SF, LF, CR, RPT, EPI_CLOV_XPAY_CG, RPH, SHL>(a, grid, block, st);
+            return hop_launch_t<SF, LF, CR, RPT, EPI_CLOV_XPAY_CG, RPH, SHL, FL>(a, grid, block,
+                                                                               st);
     }
     return hipErrorInvalidValue;
+}
+
+// The FLIC hop (thin links a.gauge, fat links a.gauge_fat, both in format LF): one rhs
+// per lane, links loaded per lane.
+template <SpinorFmt SF, LinkFmt LF, typename CR>
+hipError_t hop_launch_flic_fmt(const HopArgs &a, int rpt, int grid, int block, hipStream_t st) {
+    if (rpt != 1 || a.stage_links || !a.gauge_fat) return hipErrorInvalidValue;
+    bool real_phase = true;
+    for (int mu = 0; mu < 4; ++mu) real_phase &= a.phase[mu].y == 0.0;
+    if (real_phase) return hop_launch_epi<SF, LF, CR, 1, true, false, true>(a, grid, block, st);
+    return hop_launch_epi<SF, LF, CR, 1, false, false, true>(a, grid, block, st);
 }
 
 template <SpinorFmt SF, LinkFmt LF, typename CR>

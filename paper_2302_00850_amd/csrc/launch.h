@@ -89,9 +89,29 @@ hipError_t launch_gram(int S, int n, SpinorFmt fa, SpinorFmt fb, const void *A, 
 // X_b += sum_a P_a alpha_ab, R_b -= sum_a Q_a alpha_ab (alpha row-major complex FP64)
 hipError_t launch_block_axpy(int S, int n, SpinorFmt fx, SpinorFmt fp, void *X, const void *P,
                              void *R, const void *Q, const double *alpha, hipStream_t st);
+// Z = H^-1 B over the active columns (bit mask act), H and B Gram results (transposed
+// layout), pivots below 1e-13 of the largest diagonal deflated; Z row-major (one thread)
+hipError_t launch_block_solve(const double *H, const double *B, unsigned act, int n, double *Z,
+                              hipStream_t st);
 // Pn_b = R_b + sum_a P_a beta_ab
 hipError_t launch_block_xpay(int S, int n, SpinorFmt fr, SpinorFmt fp, void *Pn, const void *R,
                              const void *P, const double *beta, hipStream_t st);
+
+// --- low-eigenmode solver: one-rhs FP64 packed fields as flat arrays of n complex values
+constexpr int kEigChunk = 8;        // vectors per dot / linear-combination launch
+constexpr int kEigMaxBlocks = 2048; // blocks of a dot launch (partials: 2 kEigChunk each)
+struct EigVecs {
+    const Cplx64 *v[kEigChunk];
+};
+struct EigCoef {
+    Cplx64 c[kEigChunk];
+};
+// result[2j], result[2j+1] = Re, Im <V_j, w> for j < k <= kEigChunk (partial: handle buffer)
+hipError_t launch_eig_dots(const EigVecs &V, int k, const void *w, size_t n, double *partial,
+                           double *result, hipStream_t st);
+// out = a out + sum_{j<k} c_j V_j (a = 0: out is not read; out may be one of the V_j)
+hipError_t launch_eig_lincomb(void *out, double are, double aim, const EigVecs &V,
+                              const EigCoef &c, int k, size_t n, hipStream_t st);
 
 // --- clover
 // Builds A = 1 - kappa csw sum sigma F (two 6x6 chiral blocks) and A^-1 per site from
@@ -111,8 +131,11 @@ hipError_t launch_gauge_force(const Geom &g, const void *U, void *F, double beta
 // P -= eps (F1 + F2) over nlinks 3x3 matrices (F2 may be null)
 hipError_t launch_momentum_update(void *P, const void *F1, const void *F2, double eps,
                                   size_t nlinks, hipStream_t st);
-// U <- exp(i eps P) U over nlinks links
+// U <- exp(i eps P) U over nlinks links, rows re-orthonormalised (row 2 = conj(row0 x row1))
 hipError_t launch_link_update(void *U, const void *P, double eps, size_t nlinks, hipStream_t st);
+// one APE smearing sweep Out = P_SU3[(1 - alpha) U + alpha/6 staples] (Out != U)
+hipError_t launch_ape_sweep(const Geom &g, const void *U, void *Out, double alpha,
+                            hipStream_t st);
 // *result (device) = sum over sites and mu < nu of Re Tr U_plaq
 hipError_t launch_plaquette_sum(const Geom &g, const void *U, double *partial, double *result,
                                 hipStream_t st);

@@ -5,6 +5,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include "handle.h"
 
@@ -70,6 +74,17 @@ Reduce reduce_into(cola_handle_t *h, int slot) {
     return Reduce{h->partial, h->counter, scal_slot(h, slot)};
 }
 
+// The file of tuned shapes: $COLA_TUNE_CACHE (empty: none), else
+// $XDG_CACHE_HOME/cola/hop_tune.txt or ~/.cache/cola/hop_tune.txt.
+std::string tune_cache_path() {
+    if (const char *p = getenv("COLA_TUNE_CACHE")) return p;
+    if (const char *x = getenv("XDG_CACHE_HOME"))
+        if (x[0]) return std::string(x) + "/cola/hop_tune.txt";
+    if (const char *hm = getenv("HOME"))
+        if (hm[0]) return std::string(hm) + "/.cache/cola/hop_tune.txt";
+    return "";
+}
+
 std::string tune_key(const cola_handle_t *h, int prec, int nrhs, int epi, int norm) {
     char buf[160];
     snprintf(buf, sizeof buf, "hop:%dx%dx%dx%d:p%d:r%d:e%d:n%d", h->dims[0], h->dims[1],
@@ -86,8 +101,12 @@ void hop_work(const cola_handle_t *h, int prec, int nrhs, int epi, double *bytes
     const SpinorFmt sf = spinor_fmt(prec);
     const LinkFmt lf = link_fmt(prec);
     const double Vh = h->g.Vh;
-    double b = 8.0 * link_bytes(lf) + 2.0 * nrhs * spinor_site_bytes(sf);
-    double f = 1320.0 * nrhs + (lf == LinkFmt::F64_18 ? 0.0 : 8 * 42.0);
+    // FLIC: the thin and the smeared link of each direction, two projections and four
+    // SU(3) products (twice the Wilson count) plus 36 flops to combine the links
+    const double nl = h->flic ? 2.0 : 1.0;
+    double b = 8.0 * nl * link_bytes(lf) + 2.0 * nrhs * spinor_site_bytes(sf);
+    double f = nl * 1320.0 * nrhs + nl * (lf == LinkFmt::F64_18 ? 0.0 : 8 * 42.0) +
+               (h->flic ? 8 * 36.0 : 0.0);
     const bool cg = epi == EPI_XPAY_CG || epi == EPI_CLOV_XPAY_CG;
     if (epi == EPI_XPAY || epi == EPI_CLOV_XPAY || epi == EPI_XPAY_CLOV || cg) {
         b += nrhs * spinor_site_bytes(sf);
@@ -156,6 +175,71 @@ bool stage_ok(const Geom &g, int prec, int nrhs, const TuneEntry &t) {
            bytes < 2147483648.0;
 }
 
+// A launch shape the hop kernels accept for this lattice, precision and rhs count.
+bool shape_valid(const Geom &g, int prec, int nrhs, const TuneEntry &e) {
+    const bool f64 = prec == COLA_FP64 || prec == COLA_FP64_12;
+    return (e.rpt >= 1 && e.rpt <= 4) && nrhs % e.rpt == 0 && (e.rpt == 1 || !f64) &&
+           e.sites_per_block >= 1 && (e.sites_per_block & (e.sites_per_block - 1)) == 0 &&
+           e.sites_per_block * (nrhs / e.rpt) <= 256 && e.grid >= -1 && e.tchunk >= 1 &&
+           g.L[3] % e.tchunk == 0 && tile_ok(g, e.tile_y, e.tile_z) &&
+           (e.tile_y == 0 || e.tchunk == 1);
+}
+
+// ---- the persistent table of tuned shapes
+// Shared by every handle of the process and kept in a text file (one entry per line:
+// device tag, key, rpt, sites per block, grid, time chunk, tile y, tile z, staging, ms),
+// so that shapes tuned once are used by default afterwards, in this process and later
+// ones.  Every shape gives bitwise the same result, so a stale entry can only cost
+// time; entries that do not fit the launch are ignored.
+struct TuneStore {
+    std::mutex mu;
+    std::map<std::string, TuneEntry> table;
+    bool loaded = false;
+};
+
+TuneStore &tune_store() {
+    static TuneStore s;
+    return s;
+}
+
+std::string store_key(const cola_handle_t *h, const std::string &key) {
+    return h->arch + ":" + std::to_string(h->num_cu) + " " + key;
+}
+
+int read_table(const std::string &path, std::map<std::string, TuneEntry> &out) {
+    FILE *f = fopen(path.c_str(), "r");
+    if (!f) return -1;
+    char dev[128], key[160];
+    TuneEntry e;
+    int n = 0;
+    while (fscanf(f, "%127s %159s %d %d %d %d %d %d %d %lf", dev, key, &e.rpt, &e.sites_per_block,
+                  &e.grid, &e.tchunk, &e.tile_y, &e.tile_z, &e.stage, &e.ms) == 10) {
+        out[std::string(dev) + " " + key] = e;
+        ++n;
+    }
+    fclose(f);
+    return n;
+}
+
+int write_table(const std::string &path, const std::map<std::string, TuneEntry> &t) {
+    const size_t cut = path.find_last_of('/');
+    if (cut != std::string::npos && cut > 0) {
+        // create the directory chain (mkdir -p)
+        for (size_t k = 1; k <= cut; ++k)
+            if (k == cut || path[k] == '/') mkdir(path.substr(0, k).c_str(), 0755);
+    }
+    const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return -1;
+    for (const auto &kv : t) {
+        const TuneEntry &e = kv.second;
+        fprintf(f, "%s %d %d %d %d %d %d %d %.6f\n", kv.first.c_str(), e.rpt, e.sites_per_block,
+                e.grid, e.tchunk, e.tile_y, e.tile_z, e.stage, e.ms);
+    }
+    if (fclose(f) != 0) return -1;
+    return rename(tmp.c_str(), path.c_str()) == 0 ? (int)t.size() : -1;
+}
+
 TuneEntry default_entry(const Geom &g, int prec, int nrhs) {
     TuneEntry t;
     t.rpt = 1;
@@ -201,12 +285,7 @@ TuneEntry default_entry(const Geom &g, int prec, int nrhs) {
         e.stage = -1;
         const int n = sscanf(env, "%d,%d,%d,%d,%d,%d,%d", &e.rpt, &e.sites_per_block, &e.grid,
                              &e.tchunk, &e.tile_y, &e.tile_z, &e.stage);
-        if ((n == 4 || n == 6 || n == 7) && (e.rpt >= 1 && e.rpt <= 4) && nrhs % e.rpt == 0 &&
-            (e.rpt == 1 || !f64) &&
-            e.sites_per_block >= 1 && (e.sites_per_block & (e.sites_per_block - 1)) == 0 &&
-            e.sites_per_block * (nrhs / e.rpt) <= 256 && e.grid >= -1 && e.tchunk >= 1 &&
-            g.L[3] % e.tchunk == 0 && tile_ok(g, e.tile_y, e.tile_z) &&
-            (e.tile_y == 0 || e.tchunk == 1)) {
+        if ((n == 4 || n == 6 || n == 7) && shape_valid(g, prec, nrhs, e)) {
             // staging as asked where possible, else the default rule
             const bool ok = stage_ok(g, prec, nrhs, e);
             e.stage = e.stage < 0 ? (ok ? 1 : 0) : (e.stage && ok ? 1 : 0);
@@ -245,6 +324,7 @@ int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, cons
     a.cg_pi2 = c.cg_pi2;
     a.cg_active = c.cg_active;
     a.gauge = h->gauge[(int)link_fmt(prec)];
+    a.gauge_fat = h->flic ? h->fat[(int)link_fmt(prec)] : nullptr;
     a.clov = c.clov;
     a.partial = h->partial;
     a.total = (uint32_t)(h->g.Vh / te.tchunk) * (uint32_t)groups;
@@ -288,6 +368,31 @@ int fill_and_launch(cola_handle_t *h, const HopCall &c, int prec, int nrhs, cons
     if (c.norm_result && reduce)
         COLA_HIP(h, launch_reduce_partials(h->partial, grid, nrhs, c.norm_result, st));
     return COLA_OK;
+}
+
+// The stored shape for this key, unless a shape is pinned by COLA_HOP_SHAPE or the entry
+// does not fit this launch; load: read the file once per process if not yet read.
+bool stored_entry(cola_handle_t *h, const std::string &key, int prec, int nrhs, bool load,
+                  TuneEntry *out) {
+    if (getenv("COLA_HOP_SHAPE") || h->flic) return false;
+    TuneStore &ts = tune_store();
+    std::lock_guard<std::mutex> lock(ts.mu);
+    if (!ts.loaded && load) {
+        ts.loaded = true;
+        const std::string path = tune_cache_path();
+        if (!path.empty()) {
+            std::map<std::string, TuneEntry> t;
+            if (read_table(path, t) > 0)
+                for (auto &kv : t) ts.table.emplace(kv.first, kv.second);  // keep newer
+        }
+    }
+    auto it = ts.table.find(store_key(h, key));
+    if (it == ts.table.end()) return false;
+    TuneEntry e = it->second;
+    if (!shape_valid(h->g, prec, nrhs, e)) return false;
+    if (e.stage && !stage_ok(h->g, prec, nrhs, e)) e.stage = 0;
+    *out = e;
+    return true;
 }
 
 int tune_hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, TuneEntry *best,
@@ -398,6 +503,8 @@ int hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, hipStream_t st) 
                          "compressed link formats need an SU(3) gauge field (check failed)");
     if (!h->gauge[(int)link_fmt(prec)])
         return set_error(h, COLA_EINVAL, "packed gauge field missing for this precision");
+    if (h->flic && prec == COLA_FP16)
+        return set_error(h, COLA_EINVAL, "the FLIC operator runs in FP64 and FP32");
     // The CG epilogues update their vectors in place, so they are never timed by the
     // tuner: they take the shape tuned for the epilogue they extend, else the default.
     const bool cg = c.epi == EPI_XPAY_CG || c.epi == EPI_CLOV_XPAY_CG;
@@ -409,15 +516,26 @@ int hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, hipStream_t st) 
     auto it = h->tune.find(key);
     if (it != h->tune.end() && (h->tune_mode != 2 || cg || c.fixed)) {
         te = it->second;
-    } else if (h->tune_mode >= 1 && !cg && !c.fixed) {
+    } else if (h->tune_mode >= 1 && !cg && !c.fixed && !h->flic) {
         COLA_TRY(tune_hop(h, c, prec, nrhs, &te, st));
         h->tune[key] = te;
-    } else {
+        // into the process-wide table and its file (a failed write only loses the cache)
+        TuneStore &ts = tune_store();
+        std::lock_guard<std::mutex> lock(ts.mu);
+        ts.table[store_key(h, key)] = te;
+        const std::string path = tune_cache_path();
+        if (!path.empty()) write_table(path, ts.table);
+    } else if (!stored_entry(h, key, prec, nrhs, !c.fixed, &te)) {
         te = default_entry(h->g, prec, nrhs);
     }
     // a resident grid needs an occupancy query (cached in a host map): the fixed mode
     // takes the plain grid instead, which gives bitwise the same output
     if (c.fixed && te.grid < 0) te.grid = 0;
+    // FLIC hops: one rhs per lane, both links loaded per lane
+    if (h->flic) {
+        te.rpt = 1;
+        te.stage = 0;
+    }
     const bool timed = (h->flags & COLA_FLAG_TIMING) != 0 && !c.fixed;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
@@ -443,6 +561,29 @@ int hop(cola_handle_t *h, const HopCall &c, int prec, int nrhs, hipStream_t st) 
         h->pending_epi.push_back(c.epi);
     }
     return COLA_OK;
+}
+
+int tune_cache_load(cola_handle_t *h, const char *path) {
+    const std::string p = path ? path : tune_cache_path();
+    if (p.empty()) return set_error(h, COLA_EINVAL, "no tuning cache path");
+    std::map<std::string, TuneEntry> t;
+    const int n = read_table(p, t);
+    if (n < 0) return set_error(h, COLA_EINVAL, "cannot read " + p);
+    TuneStore &ts = tune_store();
+    std::lock_guard<std::mutex> lock(ts.mu);
+    ts.loaded = true;
+    for (auto &kv : t) ts.table[kv.first] = kv.second;
+    return n;
+}
+
+int tune_cache_save(cola_handle_t *h, const char *path) {
+    const std::string p = path ? path : tune_cache_path();
+    if (p.empty()) return set_error(h, COLA_EINVAL, "no tuning cache path");
+    TuneStore &ts = tune_store();
+    std::lock_guard<std::mutex> lock(ts.mu);
+    const int n = write_table(p, ts.table);
+    if (n < 0) return set_error(h, COLA_EINVAL, "cannot write " + p);
+    return n;
 }
 
 size_t op_workspace_bytes(const cola_handle_t *h, int op, int prec, int nrhs) {

@@ -22,7 +22,6 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
-#include <complex>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -387,147 +386,76 @@ int inner_cg(const Ctx &c, int prec, SpinorFmt fx, void *x, void *r, void *pv, v
 
 // ---------------------------------------------------------------- block CG
 
-using cd = std::complex<double>;
-
-// Solve H Z = B for Hermitian positive semi-definite H (n x n) restricted to the
-// active index set, by Cholesky; pivots below 1e-13 of the largest diagonal are
-// treated as null directions (their rows of Z are set to zero), which deflates
-// linearly dependent search directions.  Inactive rows and columns of Z are 0.
-void hpsd_solve(int n, const std::vector<cd> &H, const std::vector<cd> &B,
-                const std::vector<int> &act, std::vector<cd> &Z) {
-    std::vector<int> ix;
-    for (int q = 0; q < n; ++q)
-        if (act[q]) ix.push_back(q);
-    const int m = (int)ix.size();
-    Z.assign((size_t)n * n, cd(0, 0));
-    if (m == 0) return;
-    std::vector<cd> L((size_t)m * m, cd(0, 0));
-    std::vector<char> live(m, 1);
-    double dmax = 0;
-    for (int j = 0; j < m; ++j) dmax = std::max(dmax, H[(size_t)ix[j] * n + ix[j]].real());
-    for (int j = 0; j < m; ++j) {
-        double d = H[(size_t)ix[j] * n + ix[j]].real();
-        for (int k = 0; k < j; ++k) d -= std::norm(L[(size_t)j * m + k]);
-        if (!(d > 1e-13 * dmax)) {
-            live[j] = 0;
-            continue;
-        }
-        const double ljj = std::sqrt(d);
-        L[(size_t)j * m + j] = ljj;
-        for (int i = j + 1; i < m; ++i) {
-            cd s = H[(size_t)ix[i] * n + ix[j]];
-            for (int k = 0; k < j; ++k) s -= L[(size_t)i * m + k] * std::conj(L[(size_t)j * m + k]);
-            L[(size_t)i * m + j] = s / ljj;
-        }
-    }
-    for (int col = 0; col < n; ++col) {
-        if (!act[col]) continue;
-        std::vector<cd> y(m);
-        for (int i = 0; i < m; ++i) {
-            if (!live[i]) {
-                y[i] = 0;
-                continue;
-            }
-            cd s = B[(size_t)ix[i] * n + col];
-            for (int k = 0; k < i; ++k) s -= L[(size_t)i * m + k] * y[k];
-            y[i] = s / L[(size_t)i * m + i];
-        }
-        for (int i = m - 1; i >= 0; --i) {
-            if (!live[i]) {
-                y[i] = 0;
-                continue;
-            }
-            cd s = y[i];
-            for (int k = i + 1; k < m; ++k) s -= std::conj(L[(size_t)k * m + i]) * y[k];
-            y[i] = s / L[(size_t)i * m + i];
-        }
-        for (int i = 0; i < m; ++i) Z[(size_t)ix[i] * n + col] = y[i];
-    }
-}
-
-// read an n x n Gram matrix (stored transposed by the kernel) into row-major G
-int read_gram(const Ctx &c, double *dev, double *host, std::vector<cd> &G) {
-    const int n = c.R;
-    COLA_HIP(c.h, hipMemcpyAsync(host, dev, sizeof(double) * 2 * n * n, hipMemcpyDeviceToHost,
-                                 c.st));
-    COLA_HIP(c.h, hipStreamSynchronize(c.st));
-    G.resize((size_t)n * n);
-    for (int b = 0; b < n; ++b)
-        for (int a = 0; a < n; ++a)
-            G[(size_t)a * n + b] = cd(host[(b * n + a) * 2], host[(b * n + a) * 2 + 1]);
-    return COLA_OK;
-}
-
-int upload_mat(const Ctx &c, const std::vector<cd> &Z, double *dev, double *host) {
-    const int n = c.R;
-    for (int k = 0; k < n * n; ++k) {
-        host[2 * k] = Z[k].real();
-        host[2 * k + 1] = Z[k].imag();
-    }
-    COLA_HIP(c.h, hipMemcpyAsync(dev, host, sizeof(double) * 2 * n * n, hipMemcpyHostToDevice,
-                                 c.st));
-    COLA_HIP(c.h, hipStreamSynchronize(c.st));  // the staging area is reused
-    return COLA_OK;
-}
-
 // O'Leary block CG on A E = R (R given in r32, E accumulated in x32), all active
 // columns sharing one Krylov space:
 //   Q = A P; alpha = (P^H Q)^-1 (R^H R); E += P alpha; R -= Q alpha;
 //   beta = (R^H R)_old^-1 (R^H R)_new; P = R + P beta.
-// Stops when every active column's |R_q|^2 <= inner_tol2 (the columns start at 1).
+// The Gram matrices and the two small Hermitian solves (Cholesky with deflation of
+// dependent directions, block_solve_kernel) stay on the device; the host reads the
+// diagonal of R^H R every `check` iterations to stop once every active column's
+// |R_q|^2 <= inner_tol2 (the columns start at 1).
 int inner_block_cg(const Ctx &c, int prec, void *x32, void *r32,
                    const std::vector<double> &inner_tol2, int max_it, std::vector<int> act,
-                   int *iters, int *status) {
+                   int check, int *iters, int *status) {
     cola_handle_t *h = c.h;
     const int n = c.R;
     const SpinorFmt fp = spinor_fmt(prec);
     const SpinorFmt fx = SpinorFmt::F32;
     const int S = h->g.S;
-    void *P, *Pn, *Q, *gbuf, *mbuf;
+    void *P, *Pn, *Q, *mats;
     COLA_TRY(vec(c, "bP", fp, &P));
     COLA_TRY(vec(c, "bPn", fp, &Pn));
     COLA_TRY(vec(c, "bQ", fp, &Q));
-    COLA_TRY(get_vec(h, "gram_result", sizeof(double) * 2 * kMaxRhs * kMaxRhs, &gbuf));
-    COLA_TRY(get_vec(h, "gram_mat", sizeof(double) * 2 * kMaxRhs * kMaxRhs, &mbuf));
-    std::vector<double> host(2 * kMaxRhs * kMaxRhs);
-    const Reduce red{h->partial, h->counter, (double *)gbuf};
+    // five n x n complex matrices: P^H Q, R^H R (two, alternating), alpha, beta
+    const size_t mat = (size_t)2 * kMaxRhs * kMaxRhs;
+    COLA_TRY(get_vec(h, "block_mats", sizeof(double) * 5 * mat, &mats));
+    double *Gpi = (double *)mats, *Grho[2] = {Gpi + mat, Gpi + 2 * mat}, *alpha = Gpi + 3 * mat,
+           *beta = Gpi + 4 * mat;
+    std::vector<double> host(2 * (size_t)n * n);
+    unsigned mask_bits = 0;
     // inactive columns take no part: zero their residual so they stay at E = 0
     std::vector<double> mask(n);
-    for (int q = 0; q < n; ++q) mask[q] = act[q] ? 1.0 : 0.0;
+    for (int q = 0; q < n; ++q) {
+        mask[q] = act[q] ? 1.0 : 0.0;
+        if (act[q]) mask_bits |= 1u << q;
+    }
     COLA_TRY(write_slot(c, TMP, mask));
     const BlasShape sh = c.shape();
     COLA_HIP(h, launch_convert(sh, fx, fx, r32, r32, c.slot(TMP), 0, nullptr, c.st));
     COLA_HIP(h, launch_convert(sh, fp, fx, P, r32, nullptr, 0, nullptr, c.st));
-    std::vector<cd> rho, rho_new, Pi, alpha, beta;
-    COLA_HIP(h, launch_gram(S, n, fx, fx, r32, r32, red, c.st));
-    COLA_TRY(read_gram(c, (double *)gbuf, host.data(), rho));
+    auto gram = [&](SpinorFmt fa, SpinorFmt fb, const void *A, const void *B, double *out) {
+        return launch_gram(S, n, fa, fb, A, B, Reduce{h->partial, h->counter, out}, c.st);
+    };
+    int cur = 0;
+    COLA_HIP(h, gram(fx, fx, r32, r32, Grho[cur]));
     int it = 0;
     while (it < max_it) {
         COLA_TRY(normal(c, prec, Q, P));
-        COLA_HIP(h, launch_gram(S, n, fp, fp, P, Q, red, c.st));
-        COLA_TRY(read_gram(c, (double *)gbuf, host.data(), Pi));
-        hpsd_solve(n, Pi, rho, act, alpha);
-        COLA_TRY(upload_mat(c, alpha, (double *)mbuf, host.data()));
-        COLA_HIP(h, launch_block_axpy(S, n, fx, fp, x32, P, r32, Q, (const double *)mbuf, c.st));
+        COLA_HIP(h, gram(fp, fp, P, Q, Gpi));
+        COLA_HIP(h, launch_block_solve(Gpi, Grho[cur], mask_bits, n, alpha, c.st));
+        COLA_HIP(h, launch_block_axpy(S, n, fx, fp, x32, P, r32, Q, alpha, c.st));
         ++it;
-        COLA_HIP(h, launch_gram(S, n, fx, fx, r32, r32, red, c.st));
-        COLA_TRY(read_gram(c, (double *)gbuf, host.data(), rho_new));
-        bool any = false, bad = false;
-        for (int q = 0; q < n; ++q) {
-            const double d = rho_new[(size_t)q * n + q].real();
-            bad |= !std::isfinite(d);
-            any |= act[q] && d > inner_tol2[q];
+        COLA_HIP(h, gram(fx, fx, r32, r32, Grho[1 - cur]));
+        if (it % check == 0 || it == max_it) {
+            COLA_HIP(h, hipMemcpyAsync(host.data(), Grho[1 - cur], sizeof(double) * host.size(),
+                                       hipMemcpyDeviceToHost, c.st));
+            COLA_HIP(h, hipStreamSynchronize(c.st));
+            bool any = false, bad = false;
+            for (int q = 0; q < n; ++q) {
+                const double d = host[2 * (q * n + q)];  // (R^H R)_qq
+                bad |= !std::isfinite(d);
+                any |= act[q] && d > inner_tol2[q];
+            }
+            if (bad) {
+                *status = COLA_BREAKDOWN;
+                break;
+            }
+            if (!any) break;
         }
-        if (bad) {
-            *status = COLA_BREAKDOWN;
-            break;
-        }
-        if (!any) break;
-        hpsd_solve(n, rho, rho_new, act, beta);
-        COLA_TRY(upload_mat(c, beta, (double *)mbuf, host.data()));
-        COLA_HIP(h, launch_block_xpay(S, n, fx, fp, Pn, r32, P, (const double *)mbuf, c.st));
+        COLA_HIP(h, launch_block_solve(Grho[cur], Grho[1 - cur], mask_bits, n, beta, c.st));
+        COLA_HIP(h, launch_block_xpay(S, n, fx, fp, Pn, r32, P, beta, c.st));
         std::swap(P, Pn);
-        rho.swap(rho_new);
+        cur = 1 - cur;
     }
     *iters = it;
     return COLA_OK;
@@ -609,7 +537,7 @@ int solve_defect(const Ctx &c, int inner_prec, const cola_cg_params_t &p, void *
         int its = 0, st = COLA_OK;
         if (p.block)
             COLA_TRY(inner_block_cg(c, prec, x32, r32, itol2, p.max_iter - o->iterations, act,
-                                    &its, &st));
+                                    check, &its, &st));
         else
             COLA_TRY(inner_cg(c, prec, fxr, xs, rs, pv, ap, itol2, p.max_iter - o->iterations,
                               act, check, &its, &st));

@@ -10,6 +10,10 @@ if ROOT not in sys.path:
 
 
 def pytest_configure(config):
+    # tuned launch shapes go to a file of this run, not the user's cache
+    import tempfile
+    os.environ.setdefault("COLA_TUNE_CACHE",
+                          os.path.join(tempfile.mkdtemp(prefix="cola_tune_"), "hop_tune.txt"))
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long CPU test")
 

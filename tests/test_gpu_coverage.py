@@ -257,7 +257,7 @@ def test_block_cg_c3_propagator_sampled_residual():
 # ------------------------------------------------------------------ tuner
 
 @pytest.mark.parametrize("prec", [cola.COLA_FP32, cola.COLA_FP16])
-def test_tuner_bitwise_and_tuned_solve(prec):
+def test_tuner_bitwise_and_tuned_solve(prec, tmp_path):
     """With tuning on, the first use of each hop key times every candidate launch shape
     and keeps the fastest; any shape gives bitwise the default shape's output.  A solve
     with tuned shapes reaches the tolerance the oracle recomputes."""
@@ -279,6 +279,20 @@ def test_tuner_bitwise_and_tuned_solve(prec):
     out2 = tuned.empty_packed(prec, 12, 0)
     tuned.dslash(out2, pin, cola.COLA_OP_HOP, 0, prec, 12)  # the cached shape
     assert torch.equal(out, ref) and torch.equal(out2, ref)
+    # the tuned shapes persist: written to a file, read back by a fresh handle, whose hop
+    # (tuning off) then takes the stored shape -- still bitwise the default output
+    path = str(tmp_path / "tune.txt")
+    n = cola.cola_tune_save(tuned.h, path)
+    assert n >= 1
+    assert any(f"hop:{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]}:p{prec}:r12" in line
+               for line in open(path))
+    fresh = cola.Lattice(dims, kappa, ANTI)
+    fresh.set_gauge(_cuda(U))
+    assert cola.cola_tune_load(fresh.h, path) == n
+    out3 = fresh.empty_packed(prec, 12, 0)
+    fresh.dslash(out3, pin, cola.COLA_OP_HOP, 0, prec, 12)
+    assert torch.equal(out3, ref)
+    fresh.close()
     b = point_sources(dims).numpy()
     scheme = cola.COLA_CG_FP32_DEFECT if prec == cola.COLA_FP32 else cola.COLA_CG_FP16_DEFECT
     x, info = tuned.cg(_cuda(b), system=cola.COLA_SYS_PROPAGATOR, scheme=scheme, tol=1e-10)

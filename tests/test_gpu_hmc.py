@@ -182,3 +182,36 @@ def test_quenched_sampler_reaches_the_known_plaquette():
             plaq.append(1.0 - lat.gauge_action(U, beta) / (beta * 6 * V))
     assert abs(np.mean(w) - 1.0) < 0.05
     assert 0.58 < np.mean(plaq) < 0.63
+
+
+def test_long_run_links_stay_su3():
+    """250 even-odd Omelyan trajectories with FP32 reliable-update solves (momenta
+    refreshed each time, every trajectory kept): the link update re-unitarises, so the
+    field still passes the SU(3) check that the mixed-precision solves require, and the
+    next trajectory from the evolved field is still the oracle's."""
+    dims = (4, 4, 4, 4)
+    s = Synth(91)
+    U = s.gauge(dims, mix=0.5)
+    phi = s.gaussian_spinor(dims)[0]
+    lat = cola.Lattice(dims, 0.12, ANTI)
+    Ud, phid = U.cuda(), phi.cuda()
+    for k in range(250):
+        Pd = s.momenta(dims).cuda()
+        info = lat.hmc_trajectory(Ud, Pd, BETA, 0.1, 4, phi=phid, cg_tol=1e-10, eo=True,
+                                  integrator="omelyan", cg_scheme=cola.COLA_CG_FP32_RELIABLE)
+        assert info["status"] == cola.COLA_OK, (k, info)
+    Uh = Ud.cpu().numpy()
+    dev = np.abs(np.einsum("...ij,...kj->...ik", Uh, Uh.conj()) - np.eye(3)).max()
+    assert dev < 1e-13, dev
+    assert np.abs(np.linalg.det(Uh) - 1).max() < 1e-13
+    lat.set_gauge(Ud)
+    assert lat.gauge_is_su3
+    P = s.momenta(dims).numpy()
+    U1, P1, H0, H1 = hmc.trajectory(Uh, P, BETA, 0.1, 4, phi=phi.numpy(), kappa=0.12, bc=ANTI,
+                                    tol=1e-13, eo=True, integrator="omelyan")
+    Pd = _cuda(P)
+    info = lat.hmc_trajectory(Ud, Pd, BETA, 0.1, 4, phi=phid, cg_tol=1e-13, eo=True,
+                              integrator="omelyan")
+    assert info["status"] == cola.COLA_OK
+    assert np.abs(Ud.cpu().numpy() - U1).max() < 1e-10
+    assert info["dH"] == pytest.approx(H1 - H0, abs=1e-7)
