@@ -290,8 +290,10 @@ int cola_cg_multishift(cola_handle_t *h, void *x, const void *b, int nshift, con
  * on entry (linearly independent; SCHUR reads their even sites) and the orthonormal
  * eigenvectors on return (SCHUR: odd sites zero), ascending eigenvalues in
  * r->eigenvalues.  n = 1 .. 32.  Returns COLA_OK, COLA_NOT_CONVERGED (the current
- * vectors and Ritz values are returned), COLA_BREAKDOWN (dependent or non-finite
- * starting vectors; X unchanged) or < 0: COLA_EINVAL for another system, n out of
+ * vectors and Ritz values are returned), COLA_BREAKDOWN (a vector with nothing left
+ * once the vectors before it are projected out, as a zero start or one in the span of
+ * the starts before it that have not moved yet, or non-finite values; X unchanged) or
+ * < 0: COLA_EINVAL for another system, n out of
  * range, tol <= 0 or csw-free requirements unmet, COLA_ESTATE without a gauge field.
  * Synchronises `stream`. */
 int cola_eigensolve(cola_handle_t *h, void *X, int n, const cola_eig_params_t *p,

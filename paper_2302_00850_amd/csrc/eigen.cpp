@@ -164,8 +164,8 @@ int eigensolve_impl(cola_handle_t *h, void *Xc, int nv, const cola_eig_params_t 
             COLA_TRY(norm(e, x, &n0));
             COLA_TRY(project(e, X, i, x));
             COLA_TRY(norm(e, x, &nx));
-            // nothing left after removing the earlier vectors (beyond rounding): the
-            // vectors are linearly dependent
+            // nothing left after removing the earlier vectors (beyond rounding): x_i lies
+            // in their span
             if (!(nx > 1e-10 * n0) || !std::isfinite(nx))
                 return set_error(h, COLA_BREAKDOWN,
                                  "starting vectors are linearly dependent or not finite");

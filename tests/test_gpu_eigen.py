@@ -115,9 +115,11 @@ def test_eigensolve_argument_errors():
         lat.eigensolve(X0, system=cola.COLA_SYS_PROPAGATOR)
     with pytest.raises(cola.ColaError):
         lat.eigensolve(X0, tol=0.0)
-    # dependent starting vectors: a breakdown status, nothing raised
-    dup = torch.stack([X0[0], X0[0]])
-    lam, X, info = lat.eigensolve(dup)
+    # a starting vector with nothing left once the vectors before it are projected out (here
+    # a zero vector; a copy of an earlier start is not one, since that vector has moved by
+    # the time the copy is reached): a breakdown status, nothing raised
+    dead = torch.stack([X0[0], torch.zeros_like(X0[0])])
+    lam, X, info = lat.eigensolve(dead)
     assert info["status"] == cola.COLA_BREAKDOWN
 
 
