@@ -78,7 +78,7 @@ int cola_create(cola_handle_t **hp, const int dims[4], double kappa, const doubl
     for (int mu = 0; mu < 4; ++mu) g.L[mu] = dims[mu];
     g.Lxh = dims[0] / 2;
     g.Vh = (int)(V / 2);
-    g.S = (g.Vh + kStrideAlign - 1) / kStrideAlign * kStrideAlign;
+    g.S = packed_stride(g.Vh);
     g.s1 = g.Lxh;
     g.s2 = g.Lxh * dims[1];
     g.s3 = g.Lxh * dims[1] * dims[2];

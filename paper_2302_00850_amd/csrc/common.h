@@ -20,6 +20,17 @@ namespace cola {
 
 constexpr int kStrideAlign = 64;
 
+// Per-parity stride of the packed fields: the checkerboard volume rounded up to an odd
+// multiple of 64 sites.  With power-of-two lattice extents an even multiple starts the
+// component arrays (c * S * R apart) at addresses sharing many low bits, and the 24 loads
+// of one lane then pile onto the same cache sets and memory channels (the odd stride made
+// the hops 2.5-9% faster at 48^3 x 96 and 32^3 x 64).
+inline int packed_stride(int vh) {
+    int s = (vh + kStrideAlign - 1) / kStrideAlign * kStrideAlign;
+    if ((s / kStrideAlign) % 2 == 0) s += kStrideAlign;
+    return s;
+}
+
 // Division by a runtime-constant divisor with a multiply-high and a shift
 // (Granlund & Montgomery, "Division by invariant integers using
 // multiplication", PLDI 1994).  Exact for numerators below 2^31.

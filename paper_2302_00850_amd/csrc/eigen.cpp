@@ -133,6 +133,18 @@ int eigensolve_impl(cola_handle_t *h, void *Xc, int nv, const cola_eig_params_t 
     e.dres = (double *)dres;
     const int parity = full ? -1 : 0;
     const size_t canon = (size_t)h->g.Vh * 2 * 12 * 16;  // bytes of one canonical spinor
+    int napply = 0, sweeps = 0, status = COLA_NOT_CONVERGED;
+    // a breakdown leaves X as it came and reports the status in *res as well
+    auto breakdown = [&](const char *msg) {
+        if (res) {
+            res->status = COLA_BREAKDOWN;
+            res->sweeps = sweeps;
+            res->applications = napply;
+            res->seconds =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        return set_error(h, COLA_BREAKDOWN, msg);
+    };
 
     std::vector<void *> X(nv), Y(nv), T(nv);
     for (int i = 0; i < nv; ++i) {
@@ -152,7 +164,6 @@ int eigensolve_impl(cola_handle_t *h, void *Xc, int nv, const cola_eig_params_t 
     const double red = p->inner_reduction > 0 ? p->inner_reduction : 0.1;
     const int inner_max = p->inner_max > 0 ? p->inner_max : 50;
     const int max_sweeps = p->max_sweeps > 0 ? p->max_sweeps : 100;
-    int napply = 0, sweeps = 0, status = COLA_NOT_CONVERGED;
     std::vector<double> lam(nv, 0.0), resid(nv, 0.0);
     std::vector<cd> d;
 
@@ -167,8 +178,7 @@ int eigensolve_impl(cola_handle_t *h, void *Xc, int nv, const cola_eig_params_t 
             // nothing left after removing the earlier vectors (beyond rounding): x_i lies
             // in their span
             if (!(nx > 1e-10 * n0) || !std::isfinite(nx))
-                return set_error(h, COLA_BREAKDOWN,
-                                 "starting vectors are linearly dependent or not finite");
+                return breakdown("starting vectors are linearly dependent or not finite");
             COLA_TRY(lincomb(e, x, cd(1 / nx, 0), {}, {}));
             COLA_TRY(apply_A(e, y, x));
             ++napply;
@@ -207,7 +217,7 @@ int eigensolve_impl(cola_handle_t *h, void *Xc, int nv, const cola_eig_params_t 
                 COLA_TRY(dots(e, {g}, g, d));
                 const double gnew2 = d[0].real();
                 if (!std::isfinite(gnew2))
-                    return set_error(h, COLA_BREAKDOWN, "non-finite gradient");
+                    return breakdown("non-finite gradient");
                 if (std::sqrt(std::max(0.0, gnew2)) <= red * g0) break;
                 COLA_TRY(lincomb(e, pv, cd(gnew2 / gn2, 0), {g}, {cd(1, 0)}));
                 gn2 = gnew2;
