@@ -514,6 +514,9 @@ def main():
                     help="workloads mode: any of mixed, force, clover, hmc, multishift, "
                          "quenched, eigen, flic")
     ap.add_argument("--block", type=int, default=0, help="use block CG in the multi-RHS solves")
+    ap.add_argument("--inner-tol", type=float, default=0.0,
+                    help="inner relative residual reduction of the defect-correction solves "
+                         "(0: the library's default)")
     ap.add_argument("--lattice", default="32,32,32,64", help="hop mode: Lx,Ly,Lz,Lt")
     ap.add_argument("--prec", default="0,2,3", help="hop mode: precisions (0 FP64 .. 3 FP16)")
     ap.add_argument("--nrhs", default="1,12", help="hop mode: right-hand-side counts")
@@ -561,7 +564,7 @@ def main():
 
     def solve(blk):
         return lat.cg(b, system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP32_DEFECT, tol=TOL,
-                      block=blk)
+                      block=blk, inner_tol=args.inner_tol)
 
     for w in range(args.warmup):
         _, info = solve(block)
@@ -655,7 +658,8 @@ def main():
                    "nrhs": 12, "sources": "point (12 spin-colour at origin)",
                    "solver": ("block CG" if block else "lockstep 12-RHS CG")
                              + ", FP32 inner + FP64 defect correction, even-odd clover Schur",
-                   "tol": TOL, "parallelism": "none (1 GPU)",
+                   "tol": TOL, "inner_tol": args.inner_tol if args.inner_tol > 0 else 1e-5,
+                   "parallelism": "none (1 GPU)",
                    "launch_shapes": "autotuned in warmup" if tune else "library defaults"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

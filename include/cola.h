@@ -119,9 +119,13 @@ typedef struct {
                               A the system's operator, checked in FP64                   */
     int max_iter;          /* cap on (inner) iterations, summed over outer cycles       */
     int reliable_interval; /* FP32_RELIABLE: iterations between FP64 residual updates   */
-    double inner_tol;      /* DEFECT: relative residual reduction of each inner solve   */
+    double inner_tol;      /* DEFECT: relative residual reduction of each inner solve
+                              (0: 1e-2 for FP16, 1e-5 for FP32)                         */
     int use_x0;            /* 1: x holds the initial guess on entry                     */
-    int check_interval;    /* iterations between host convergence checks (0 = 8)        */
+    int check_interval;    /* iterations between host convergence checks; 0: every
+                              iteration when one iteration applies the operator to at
+                              least 2^20 site-rhs (the host wait is then negligible),
+                              else 8 (5 for FP32_RELIABLE)                              */
 } cola_cg_params_t;
 
 typedef struct {

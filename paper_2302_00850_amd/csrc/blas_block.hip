@@ -1,10 +1,14 @@
 // Block kernels for block CG on n right-hand sides held in one packed block:
 //   Gram:  G_ab = sum_sites sum_c conj(A_a) B_b              (n x n, FP64 sums)
-//   axpy:  X_b += sum_a P_a alpha_ab ;  R_b -= sum_a Q_a alpha_ab
+//   axpy:  X_b += sum_a P_a alpha_ab ;  R_b -= sum_a Q_a alpha_ab   (+ optionally R^H R)
 //   xpay:  P'_b = R_b + sum_a P_a beta_ab                    (out of place)
-// One lane per (site, column b); the lanes of one site read the same n spinors
-// of the site (one cache line per component), so each field is fetched from
-// HBM once.  Small matrices are complex FP64, row-major, in device memory.
+// Work comes in units of one component of 16 consecutive sites: in the rhs-innermost
+// layout that is 16 n consecutive elements, one per lane, so every load and store of a
+// wavefront is contiguous.  A lane keeps column b of the n x n coefficients in registers
+// (b = lane mod n, fixed because the block is 16 n lanes); the n columns of its site that
+// the mixing needs come from LDS, where each lane put its own element of the unit (two
+// buffers, alternating between units, so one barrier per unit suffices).  Small matrices
+// are complex FP64, row-major, in device memory.
 #include "device.h"
 #include "launch.h"
 
@@ -12,171 +16,180 @@ namespace cola {
 
 namespace {
 
-size_t bbytes(SpinorFmt f, int S, int R) {
-    const size_t SR = (size_t)S * R;
-    switch (f) {
-        case SpinorFmt::F64: return 12 * SR * 16;
-        case SpinorFmt::F32: return 12 * SR * 8;
-        default: return 12 * SR * 4 + SR * 4;
-    }
-}
-
-// component c of (site i, rhs r) in compute precision
-template <SpinorFmt F>
-__device__ __forceinline__ cpx<typename SpinorT<F>::real> comp(const SpinorBlock<F, true> &v, int c,
-                                                              uint32_t i, uint32_t r) {
-    const uint32_t e = i * v.nrhs + r;
-    const auto h = v.data[c * v.SR + e];
-    if constexpr (F == SpinorFmt::F16) {
-        const float s = v.norm[e];
-        return {s * (float)h.x, s * (float)h.y};
-    } else {
-        return {h.x, h.y};
-    }
-}
-
 constexpr int kMaxN = 16;
+constexpr int kUnitSites = 16;  // S is a multiple of 64, so units never straddle its end
+constexpr int kGramMaxBlocks = 2048;  // Gram partial rows (2 n^2 doubles each) per launch
 
-// The N columns of component c at site i, in compute precision: in the rhs-innermost
-// layout they are N consecutive elements (FP16: scaled by the N per-(site, rhs) scales).
-template <SpinorFmt F, int N, typename T>
-__device__ __forceinline__ void load_row(const SpinorBlock<F, true> &v, int c, uint32_t i,
-                                         cpx<T> out[N]) {
-    const size_t e = (size_t)c * v.SR + (size_t)i * N;
+// element e (= i * n + b) of component c in compute precision T (FP16: times its scale)
+template <SpinorFmt F, typename T>
+__device__ __forceinline__ cpx<T> load_elem(const SpinorBlock<F, true> &v, int c, uint32_t e) {
+    using E = typename SpinorT<F>::elem;
+    const E h = bload<E, kCpolNT>(v.comp(c), e * (uint32_t)sizeof(E));
+    if constexpr (F == SpinorFmt::F16) {
+        const float sc = bload<float, kCpolNT>(v.nrm(), e * 4u);
+        return {(T)(sc * (float)h.x), (T)(sc * (float)h.y)};
+    } else {
+        return {(T)h.x, (T)h.y};
+    }
+}
+
+template <SpinorFmt F, typename T>
+__device__ __forceinline__ void store_elem(const SpinorBlock<F, true> &v, int c, uint32_t e,
+                                           cpx<T> z) {
+    static_assert(F != SpinorFmt::F16, "element stores are for FP32 / FP64 blocks");
+    using E = typename SpinorT<F>::elem;
+    bstore<E>(v.comp(c), e * (uint32_t)sizeof(E), E{(typename SpinorT<F>::real)z.x,
+                                                   (typename SpinorT<F>::real)z.y});
+}
+
+// column b of an n x n row-major complex FP64 matrix, in precision T
+template <int N, typename T>
+__device__ __forceinline__ void load_column(const double *m, int b, cpx<T> f[N]) {
+#pragma unroll
+    for (int a = 0; a < N; ++a) f[a] = {(T)m[2 * (a * N + b)], (T)m[2 * (a * N + b) + 1]};
+}
+
+// acc_a += conj(x_a) y for the n staged elements x of the lane's site, FP64 products
+template <int N, typename T>
+__device__ __forceinline__ void gram_acc(const cpx<T> *x, cpx<T> y, double acc[2 * N]) {
 #pragma unroll
     for (int a = 0; a < N; ++a) {
-        const auto h = v.data[e + a];
-        if constexpr (F == SpinorFmt::F16) {
-            const float sc = v.norm[(size_t)i * N + a];
-            out[a] = {(T)(sc * (float)h.x), (T)(sc * (float)h.y)};
-        } else {
-            out[a] = {(T)h.x, (T)h.y};
-        }
+        const cpx<T> xa = x[a];
+        acc[2 * a] += (double)xa.x * (double)y.x + (double)xa.y * (double)y.y;
+        acc[2 * a + 1] += (double)xa.x * (double)y.y - (double)xa.y * (double)y.x;
     }
 }
 
-template <SpinorFmt F, int N, typename T>
-__device__ __forceinline__ void store_row(const SpinorBlock<F, true> &v, int c, uint32_t i,
-                                          const cpx<T> in[N]) {
-    static_assert(F != SpinorFmt::F16, "row stores are for FP32 / FP64 blocks");
-    const size_t e = (size_t)c * v.SR + (size_t)i * N;
+// The block's Gram partial: lane t holds column b of it (acc[2a], acc[2a + 1] = G_ab) for
+// site slot t / n of 16.  Slots s, s + 4, s + 8 are folded into LDS row s mod 4 in that
+// order, the lanes of slot s + 12 add that row to their own, and the 4 rows go through
+// block_sum_to_result (fixed order throughout: the same sums bit for bit every launch).
+// Four rows instead of sixteen keep the LDS of a block at 8 n^2 doubles.
+template <int N>
+__device__ __forceinline__ void gram_finish(double *lds, double (&acc)[2 * N], int t, int b,
+                                            const Reduce &red) {
+    constexpr int width = 2 * N * N;
+    const int slot = t / N, row = slot & 3, round = slot >> 2;
+    double *mine = lds + row * width + 2 * N * b;
+    for (int k = t; k < 4 * width; k += blockDim.x) lds[k] = 0.0;
+    __syncthreads();
+    for (int r = 0; r < 3; ++r) {
+        if (round == r) {
 #pragma unroll
-    for (int a = 0; a < N; ++a) v.data[e + a] = {(typename SpinorT<F>::real)in[a].x,
-                                                (typename SpinorT<F>::real)in[a].y};
-}
-
-// G_ab = sum over sites and components of conj(A_a) B_b, FP64 sums.  One lane per (site,
-// column b); per component it loads its own B_b and the site's N columns of A (contiguous).
-template <SpinorFmt FA, SpinorFmt FB, int N>
-__global__ void __launch_bounds__(256) gram_kernel(const void *A, const void *B, int S, int T,
-                                                   Reduce red) {
-    extern __shared__ double lds[];
-    const SpinorBlock<FA, true> va(A, S, N);
-    const SpinorBlock<FB, true> vb(B, S, N);
-    double acc[2 * N];
-#pragma unroll
-    for (int k = 0; k < 2 * N; ++k) acc[k] = 0.0;
-    const uint32_t total = (uint32_t)S * N;
-    const int b = threadIdx.x % N;  // blockDim = T * N, so b is fixed per lane
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += gridDim.x * blockDim.x) {
-        const uint32_t i = t / N;
-        for (int c = 0; c < 12; ++c) {
-            const auto y = comp(vb, c, i, b);
-            cpx<float> x[N];
-            if constexpr (FA == SpinorFmt::F64) {
-                cpx<double> xd[N];
-                load_row<FA, N>(va, c, i, xd);
-#pragma unroll
-                for (int a = 0; a < N; ++a) {
-                    acc[2 * a] += xd[a].x * y.x + xd[a].y * y.y;
-                    acc[2 * a + 1] += xd[a].x * y.y - xd[a].y * y.x;
-                }
-            } else {
-                load_row<FA, N>(va, c, i, x);
-#pragma unroll
-                for (int a = 0; a < N; ++a) {
-                    // conj(x) * y, the products in FP64
-                    acc[2 * a] += (double)x[a].x * y.x + (double)x[a].y * y.y;
-                    acc[2 * a + 1] += (double)x[a].x * y.y - (double)x[a].y * y.x;
-                }
-            }
+            for (int k = 0; k < 2 * N; ++k) mine[k] += acc[k];
         }
+        __syncthreads();
     }
-    // result layout: index (b * N + a) * 2 + {re, im} holds G_ab
-    block_sum_to_result<2 * N>(lds, T, 2 * N * N, threadIdx.x / N, 2 * N * b, 2 * N, acc,
+    if (round == 3) {
+#pragma unroll
+        for (int k = 0; k < 2 * N; ++k) acc[k] += mine[k];
+    }
+    __syncthreads();
+    block_sum_to_result<2 * N>(lds, 4, width, row, 2 * N * b, round == 3 ? 2 * N : 0, acc,
                                red.partial, red.counter, red.result, blockIdx.x, gridDim.x);
 }
 
-// One lane per (component, site): the site's N columns of that component are loaded
-// once (consecutive lanes take consecutive sites, so a wavefront reads contiguous
-// memory), mixed with the N x N coefficients held in LDS, and stored.
-//   X_b += sum_a P_a al_ab ;  R_b -= sum_a Q_a al_ab        (al row-major complex FP64)
-template <SpinorFmt FX, SpinorFmt FP, int N>
-__global__ void __launch_bounds__(256) block_axpy_kernel(void *X, const void *P, void *R,
-                                                         const void *Q, const double *al, int S) {
-    using TX = typename SpinorT<FX>::real;
-    __shared__ cpx<TX> A[N * N];
-    for (int k = threadIdx.x; k < N * N; k += blockDim.x) A[k] = {(TX)al[2 * k], (TX)al[2 * k + 1]};
-    __syncthreads();
-    const SpinorBlock<FX, true> vx(X, S, N), vr(R, S, N);
-    const SpinorBlock<FP, true> vp(P, S, N), vq(Q, S, N);
-    const uint32_t total = 12u * (uint32_t)S;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += gridDim.x * blockDim.x) {
-        const int c = (int)(t / (uint32_t)S);
-        const uint32_t i = t - (uint32_t)c * (uint32_t)S;
-        // keeps the coefficient reads from LDS inside the loop: hoisted, the N x N complex
-        // coefficients would take 2 N^2 registers
-        asm volatile("" ::: "memory");
-        cpx<TX> x[N], r[N], p[N], q[N];
-        load_row<FX, N>(vx, c, i, x);
-        load_row<FX, N>(vr, c, i, r);
-        load_row<FP, N>(vp, c, i, p);
-        load_row<FP, N>(vq, c, i, q);
+// G_ab = sum over sites and components of conj(A_a) B_b.  Lane (unit element) loads its
+// B_b and stages its A element; the site's n elements of A then come from LDS.
+template <SpinorFmt FA, SpinorFmt FB, int N>
+__global__ void __launch_bounds__(256) gram_kernel(const void *A, const void *B, int S,
+                                                   Reduce red) {
+    using T = typename SpinorT<FA>::real;
+    constexpr int W = kUnitSites * N;
+    extern __shared__ double lds[];
+    __shared__ cpx<T> sa[2][W];
+    const SpinorBlock<FA, true> va(A, S, N);
+    const SpinorBlock<FB, true> vb(B, S, N);
+    const int t = threadIdx.x, b = t % N, s0 = t - b;
+    double acc[2 * N];
 #pragma unroll
-        for (int b = 0; b < N; ++b) {
-#pragma unroll
-            for (int a = 0; a < N; ++a) {
-                const cpx<TX> f = A[a * N + b];
-                x[b] = cmadd(x[b], p[a], f);
-                r[b] = cmadd(r[b], cpx<TX>{-q[a].x, -q[a].y}, f);
-            }
-        }
-        store_row<FX, N>(vx, c, i, x);
-        store_row<FX, N>(vr, c, i, r);
+    for (int k = 0; k < 2 * N; ++k) acc[k] = 0.0;
+    const uint32_t chunks = (uint32_t)S / kUnitSites, units = 12u * chunks;
+    const bool same = A == B;  // A^H A: the lane's B element is its staged A element
+    int buf = 0;
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x, buf ^= 1) {
+        const int c = (int)(u / chunks);
+        const uint32_t e = (u - (uint32_t)c * chunks) * W + t;
+        const cpx<T> x = load_elem<FA, T>(va, c, e);
+        const cpx<T> y = same ? x : load_elem<FB, T>(vb, c, e);
+        sa[buf][t] = x;
+        __syncthreads();
+        gram_acc<N>(&sa[buf][s0], y, acc);
     }
+    // result layout: index (b * N + a) * 2 + {re, im} holds G_ab
+    gram_finish<N>(lds, acc, t, b, red);
 }
 
-// Pn_b = R_b + sum_a P_a be_ab (one lane per (component, site), as block_axpy_kernel);
-// FP32 / FP64 directions
+//   X_b += sum_a P_a al_ab ;  R_b -= sum_a Q_a al_ab        (al row-major complex FP64)
+// GRAM: also G = R^H R of the updated R into red (as gram_kernel), from a second staging
+// of the unit (the updated R elements) after a second barrier.
+template <SpinorFmt FX, SpinorFmt FP, int N, bool GRAM>
+__global__ void __launch_bounds__(256) block_axpy_kernel(void *X, const void *P, void *R,
+                                                         const void *Q, const double *al, int S,
+                                                         Reduce red) {
+    using TX = typename SpinorT<FX>::real;
+    constexpr int W = kUnitSites * N;
+    extern __shared__ double lds[];
+    __shared__ cpx<TX> sp[2][W], sq[2][W];
+    __shared__ cpx<TX> sr[GRAM ? 2 : 1][GRAM ? W : 1];
+    const SpinorBlock<FX, true> vx(X, S, N), vr(R, S, N);
+    const SpinorBlock<FP, true> vp(P, S, N), vq(Q, S, N);
+    const int t = threadIdx.x, b = t % N, s0 = t - b;
+    cpx<TX> f[N];
+    load_column<N>(al, b, f);
+    double acc[GRAM ? 2 * N : 1];
+#pragma unroll
+    for (int k = 0; k < (GRAM ? 2 * N : 1); ++k) acc[k] = 0.0;
+    const uint32_t chunks = (uint32_t)S / kUnitSites, units = 12u * chunks;
+    int buf = 0;
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x, buf ^= 1) {
+        const int c = (int)(u / chunks);
+        const uint32_t e = (u - (uint32_t)c * chunks) * W + t;
+        cpx<TX> x = load_elem<FX, TX>(vx, c, e);
+        cpx<TX> r = load_elem<FX, TX>(vr, c, e);
+        sp[buf][t] = load_elem<FP, TX>(vp, c, e);
+        sq[buf][t] = load_elem<FP, TX>(vq, c, e);
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            const cpx<TX> pa = sp[buf][s0 + a], qa = sq[buf][s0 + a];
+            x = cmadd(x, pa, f[a]);
+            r = cmadd(r, cpx<TX>{-qa.x, -qa.y}, f[a]);
+        }
+        store_elem<FX>(vx, c, e, x);
+        store_elem<FX>(vr, c, e, r);
+        if constexpr (GRAM) {
+            sr[buf][t] = r;
+            __syncthreads();
+            gram_acc<N>(&sr[buf][s0], r, acc);
+        }
+    }
+    if constexpr (GRAM) gram_finish<N>(lds, acc, t, b, red);
+}
 
+// Pn_b = R_b + sum_a P_a be_ab, FP32 / FP64 directions (one lane per unit element)
 template <SpinorFmt FR, SpinorFmt FP, int N>
 __global__ void __launch_bounds__(256) block_xpay_kernel(void *Pn, const void *R, const void *P,
                                                          const double *be, int S) {
     using TP = typename SpinorT<FP>::real;
-    __shared__ cpx<TP> B[N * N];
-    for (int k = threadIdx.x; k < N * N; k += blockDim.x) B[k] = {(TP)be[2 * k], (TP)be[2 * k + 1]};
-    __syncthreads();
+    constexpr int W = kUnitSites * N;
+    __shared__ cpx<TP> sp[2][W];
     const SpinorBlock<FR, true> vr(R, S, N);
     const SpinorBlock<FP, true> vp(P, S, N), vo(Pn, S, N);
-    const uint32_t total = 12u * (uint32_t)S;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += gridDim.x * blockDim.x) {
-        const int c = (int)(t / (uint32_t)S);
-        const uint32_t i = t - (uint32_t)c * (uint32_t)S;
-        asm volatile("" ::: "memory");  // as in block_axpy_kernel
-        cpx<TP> r[N], p[N], o[N];
-        load_row<FR, N>(vr, c, i, r);
-        load_row<FP, N>(vp, c, i, p);
+    const int t = threadIdx.x, b = t % N, s0 = t - b;
+    cpx<TP> f[N];
+    load_column<N>(be, b, f);
+    const uint32_t chunks = (uint32_t)S / kUnitSites, units = 12u * chunks;
+    int buf = 0;
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x, buf ^= 1) {
+        const int c = (int)(u / chunks);
+        const uint32_t e = (u - (uint32_t)c * chunks) * W + t;
+        cpx<TP> o = load_elem<FR, TP>(vr, c, e);
+        sp[buf][t] = load_elem<FP, TP>(vp, c, e);
+        __syncthreads();
 #pragma unroll
-        for (int b = 0; b < N; ++b) {
-            cpx<TP> s = r[b];
-#pragma unroll
-            for (int a = 0; a < N; ++a) s = cmadd(s, p[a], B[a * N + b]);
-            o[b] = s;
-        }
-        store_row<FP, N>(vo, c, i, o);
+        for (int a = 0; a < N; ++a) o = cmadd(o, sp[buf][s0 + a], f[a]);
+        store_elem<FP>(vo, c, e, o);
     }
 }
 
@@ -194,14 +207,12 @@ __global__ void __launch_bounds__(256) block_xpay_h_kernel(void *Pn, const void 
         const int b = (int)(t - i * n);
         cpx<float> o[12];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            const auto r = comp(vr, c, i, b);
-            o[c] = {(float)r.x, (float)r.y};
-        }
+        for (int c = 0; c < 12; ++c) o[c] = load_elem<FR, float>(vr, c, t);
         for (int a = 0; a < n; ++a) {
             const cpx<float> f = {(float)be[2 * (a * n + b)], (float)be[2 * (a * n + b) + 1]};
 #pragma unroll
-            for (int c = 0; c < 12; ++c) o[c] = cmadd(o[c], comp(vp, c, i, a), f);
+            for (int c = 0; c < 12; ++c)
+                o[c] = cmadd(o[c], load_elem<SpinorFmt::F16, float>(vp, c, i * n + a), f);
         }
         vo.store(i, b, o);
     }
@@ -277,16 +288,12 @@ __global__ void __launch_bounds__(64) block_solve_kernel(const double *Hg, const
     }
 }
 
-struct Shape {
-    int T, grid;
-};
-
-Shape shape(int S, int n) {
-    int T = 1;
-    while (T * 2 * n <= 256) T *= 2;
-    size_t grid = ((size_t)S * n + (size_t)T * n - 1) / ((size_t)T * n);
-    if (grid > 2048) grid = 2048;
-    return {T, (int)(grid < 1 ? 1 : grid)};
+// Blocks for a unit kernel: a grid-stride loop over 12 S / 16 units; the reducing kernels
+// stay within the Gram partial rows.
+int unit_grid(int S, bool reduce) {
+    const size_t units = (size_t)12 * (S / kUnitSites);
+    const size_t cap = reduce ? kGramMaxBlocks : 4096;
+    return (int)(units < cap ? (units < 1 ? 1 : units) : cap);
 }
 
 }  // namespace
@@ -296,13 +303,13 @@ Shape shape(int S, int n) {
 
 template <SpinorFmt FA, SpinorFmt FB>
 hipError_t gram_n(int S, int n, const void *A, const void *B, const Reduce &red, hipStream_t st) {
-    const Shape sh = shape(S, n);
-    const size_t shm = (size_t)sh.T * 2 * n * n * sizeof(double);
+    const size_t shm = (size_t)4 * 2 * n * n * sizeof(double);
+    const int grid = unit_grid(S, true);
     switch (n) {
 #define CASE(K)                                                                               \
     case K:                                                                                   \
-        hipLaunchKernelGGL((gram_kernel<FA, FB, K>), dim3(sh.grid), dim3(sh.T * K), shm, st, A, \
-                           B, S, sh.T, red);                                                  \
+        hipLaunchKernelGGL((gram_kernel<FA, FB, K>), dim3(grid), dim3(kUnitSites * K), shm, st, \
+                           A, B, S, red);                                                     \
         break;
         COLA_BLOCK_N(CASE)
 #undef CASE
@@ -313,7 +320,7 @@ hipError_t gram_n(int S, int n, const void *A, const void *B, const Reduce &red,
 
 hipError_t launch_gram(int S, int n, SpinorFmt fa, SpinorFmt fb, const void *A, const void *B,
                        const Reduce &red, hipStream_t st) {
-    if (n < 1 || n > kMaxN || fa != fb) return hipErrorInvalidValue;
+    if (n < 1 || n > kMaxN || fa != fb || S % kUnitSites) return hipErrorInvalidValue;
     switch (fa) {
         case SpinorFmt::F64: return gram_n<SpinorFmt::F64, SpinorFmt::F64>(S, n, A, B, red, st);
         case SpinorFmt::F32: return gram_n<SpinorFmt::F32, SpinorFmt::F32>(S, n, A, B, red, st);
@@ -324,14 +331,19 @@ hipError_t launch_gram(int S, int n, SpinorFmt fa, SpinorFmt fb, const void *A, 
 
 template <SpinorFmt FX, SpinorFmt FP>
 hipError_t axpy_n(int S, int n, void *X, const void *P, void *R, const void *Q,
-                  const double *alpha, hipStream_t st) {
-    size_t grid = ((size_t)12 * S + 255) / 256;
-    if (grid > 8192) grid = 8192;
+                  const double *alpha, const Reduce *gram, hipStream_t st) {
+    const Reduce red = gram ? *gram : Reduce{nullptr, nullptr, nullptr};
+    const int grid = unit_grid(S, gram != nullptr);
+    const size_t shm = gram ? (size_t)4 * 2 * n * n * sizeof(double) : 0;
     switch (n) {
 #define CASE(K)                                                                               \
     case K:                                                                                   \
-        hipLaunchKernelGGL((block_axpy_kernel<FX, FP, K>), dim3(grid), dim3(256), 0, st, X, P, \
-                           R, Q, alpha, S);                                                   \
+        if (gram)                                                                             \
+            hipLaunchKernelGGL((block_axpy_kernel<FX, FP, K, true>), dim3(grid),              \
+                               dim3(kUnitSites * K), shm, st, X, P, R, Q, alpha, S, red);     \
+        else                                                                                  \
+            hipLaunchKernelGGL((block_axpy_kernel<FX, FP, K, false>), dim3(grid),             \
+                               dim3(kUnitSites * K), 0, st, X, P, R, Q, alpha, S, red);       \
         break;
         COLA_BLOCK_N(CASE)
 #undef CASE
@@ -341,14 +353,15 @@ hipError_t axpy_n(int S, int n, void *X, const void *P, void *R, const void *Q,
 }
 
 hipError_t launch_block_axpy(int S, int n, SpinorFmt fx, SpinorFmt fp, void *X, const void *P,
-                             void *R, const void *Q, const double *alpha, hipStream_t st) {
-    if (n < 1 || n > kMaxN) return hipErrorInvalidValue;
+                             void *R, const void *Q, const double *alpha, const Reduce *gram,
+                             hipStream_t st) {
+    if (n < 1 || n > kMaxN || S % kUnitSites) return hipErrorInvalidValue;
     if (fx == SpinorFmt::F32 && fp == SpinorFmt::F16)
-        return axpy_n<SpinorFmt::F32, SpinorFmt::F16>(S, n, X, P, R, Q, alpha, st);
+        return axpy_n<SpinorFmt::F32, SpinorFmt::F16>(S, n, X, P, R, Q, alpha, gram, st);
     if (fx == SpinorFmt::F32 && fp == SpinorFmt::F32)
-        return axpy_n<SpinorFmt::F32, SpinorFmt::F32>(S, n, X, P, R, Q, alpha, st);
+        return axpy_n<SpinorFmt::F32, SpinorFmt::F32>(S, n, X, P, R, Q, alpha, gram, st);
     if (fx == SpinorFmt::F64 && fp == SpinorFmt::F64)
-        return axpy_n<SpinorFmt::F64, SpinorFmt::F64>(S, n, X, P, R, Q, alpha, st);
+        return axpy_n<SpinorFmt::F64, SpinorFmt::F64>(S, n, X, P, R, Q, alpha, gram, st);
     return hipErrorInvalidValue;
 }
 
@@ -362,13 +375,12 @@ hipError_t launch_block_solve(const double *H, const double *B, unsigned act, in
 template <SpinorFmt FR, SpinorFmt FP>
 hipError_t xpay_n(int S, int n, void *Pn, const void *R, const void *P, const double *beta,
                   hipStream_t st) {
-    size_t grid = ((size_t)12 * S + 255) / 256;
-    if (grid > 8192) grid = 8192;
+    const int grid = unit_grid(S, false);
     switch (n) {
 #define CASE(K)                                                                                \
     case K:                                                                                    \
-        hipLaunchKernelGGL((block_xpay_kernel<FR, FP, K>), dim3(grid), dim3(256), 0, st, Pn, R, \
-                           P, beta, S);                                                        \
+        hipLaunchKernelGGL((block_xpay_kernel<FR, FP, K>), dim3(grid), dim3(kUnitSites * K), 0, \
+                           st, Pn, R, P, beta, S);                                             \
         break;
         COLA_BLOCK_N(CASE)
 #undef CASE
@@ -381,9 +393,10 @@ hipError_t launch_block_xpay(int S, int n, SpinorFmt fr, SpinorFmt fp, void *Pn,
                              const void *P, const double *beta, hipStream_t st) {
     if (n < 1 || n > kMaxN) return hipErrorInvalidValue;
     if (fr == SpinorFmt::F32 && fp == SpinorFmt::F16) {
-        const Shape sh = shape(S, n);
-        hipLaunchKernelGGL((block_xpay_h_kernel<SpinorFmt::F32>), dim3(sh.grid), dim3(sh.T * n), 0,
-                           st, Pn, R, P, beta, S, n);
+        size_t grid = ((size_t)S * n + 255) / 256;
+        if (grid > 8192) grid = 8192;
+        hipLaunchKernelGGL((block_xpay_h_kernel<SpinorFmt::F32>), dim3(grid), dim3(256), 0, st,
+                           Pn, R, P, beta, S, n);
         return hipGetLastError();
     }
     if (fr == SpinorFmt::F32 && fp == SpinorFmt::F32)

@@ -55,6 +55,17 @@ struct Ctx {
     double *slot(int s) const { return scal_slot(h, s); }
 };
 
+// Iterations between host convergence checks when the caller leaves it to the library.
+// A check reads the residual norms back and waits for them (some 10-20 us during which
+// the device idles), and the solve stops only at a check, overshooting by up to
+// check - 1 iterations.  Where an iteration moves at least 2^20 site-rhs through the
+// operator (a millisecond or more) the wait costs under 2% and every iteration is
+// checked; smaller solves check every `small` iterations.
+int default_check(const Ctx &c, int small) {
+    const double work = (double)c.h->g.Vh * c.R * c.nblk();
+    return work >= 1048576.0 ? 1 : small;
+}
+
 int vec(const Ctx &c, const char *tag, SpinorFmt f, void **out) {
     std::string t = std::string("cg_") + tag + "_" + std::to_string((int)f) + "_" +
                     std::to_string(c.R) + "_" + std::to_string(c.full);
@@ -225,7 +236,7 @@ int solve_reliable(const Ctx &c, int sloppy_prec, const cola_cg_params_t &p, voi
     const BlasShape sh = c.shape();
     const SpinorFmt fs = spinor_fmt(sloppy_prec);
     const bool same = fs == SpinorFmt::F64;
-    const int check = p.check_interval > 0 ? p.check_interval : (same ? 8 : 5);
+    const int check = p.check_interval > 0 ? p.check_interval : default_check(c, same ? 8 : 5);
     const int interval = same ? (1 << 30) : std::max(1, p.reliable_interval);
     // also update once the iterated residual has fallen by delta since the last
     // update (Clark et al.): a sloppy residual far below the true one would make
@@ -387,11 +398,13 @@ int inner_cg(const Ctx &c, int prec, SpinorFmt fx, void *x, void *r, void *pv, v
 // ---------------------------------------------------------------- block CG
 
 // O'Leary block CG on A E = R (R given in r32, E accumulated in x32), all active
-// columns sharing one Krylov space:
-//   Q = A P; alpha = (P^H Q)^-1 (R^H R); E += P alpha; R -= Q alpha;
+// columns sharing one Krylov space, A = S^H S on the even sites:
+//   T = S P, Q = S^H T; alpha = (T^H T)^-1 (R^H R); E += P alpha; R -= Q alpha;
 //   beta = (R^H R)_old^-1 (R^H R)_new; P = R + P beta.
-// The Gram matrices and the two small Hermitian solves (Cholesky with deflation of
-// dependent directions, block_solve_kernel) stay on the device; the host reads the
+// P^H Q is taken as T^H T (the same matrix, Hermitian positive semi-definite by
+// construction, and one field read instead of two).  The Gram matrices and the two small
+// Hermitian solves (Cholesky with deflation of dependent directions, block_solve_kernel)
+// stay on the device; R^H R comes out of the update kernel itself.  The host reads the
 // diagonal of R^H R every `check` iterations to stop once every active column's
 // |R_q|^2 <= inner_tol2 (the columns start at 1).
 int inner_block_cg(const Ctx &c, int prec, void *x32, void *r32,
@@ -402,11 +415,12 @@ int inner_block_cg(const Ctx &c, int prec, void *x32, void *r32,
     const SpinorFmt fp = spinor_fmt(prec);
     const SpinorFmt fx = SpinorFmt::F32;
     const int S = h->g.S;
-    void *P, *Pn, *Q, *mats;
+    void *P, *Pn, *Q, *T, *mats;
     COLA_TRY(vec(c, "bP", fp, &P));
     COLA_TRY(vec(c, "bPn", fp, &Pn));
     COLA_TRY(vec(c, "bQ", fp, &Q));
-    // five n x n complex matrices: P^H Q, R^H R (two, alternating), alpha, beta
+    COLA_TRY(vec(c, "bT", fp, &T));
+    // five n x n complex matrices: T^H T, R^H R (two, alternating), alpha, beta
     const size_t mat = (size_t)2 * kMaxRhs * kMaxRhs;
     COLA_TRY(get_vec(h, "block_mats", sizeof(double) * 5 * mat, &mats));
     double *Gpi = (double *)mats, *Grho[2] = {Gpi + mat, Gpi + 2 * mat}, *alpha = Gpi + 3 * mat,
@@ -423,19 +437,18 @@ int inner_block_cg(const Ctx &c, int prec, void *x32, void *r32,
     const BlasShape sh = c.shape();
     COLA_HIP(h, launch_convert(sh, fx, fx, r32, r32, c.slot(TMP), 0, nullptr, c.st));
     COLA_HIP(h, launch_convert(sh, fp, fx, P, r32, nullptr, 0, nullptr, c.st));
-    auto gram = [&](SpinorFmt fa, SpinorFmt fb, const void *A, const void *B, double *out) {
-        return launch_gram(S, n, fa, fb, A, B, Reduce{h->partial, h->counter, out}, c.st);
-    };
+    auto red = [&](double *out) { return Reduce{h->partial, h->counter, out}; };
     int cur = 0;
-    COLA_HIP(h, gram(fx, fx, r32, r32, Grho[cur]));
+    COLA_HIP(h, launch_gram(S, n, fx, fx, r32, r32, red(Grho[cur]), c.st));
     int it = 0;
     while (it < max_it) {
-        COLA_TRY(normal(c, prec, Q, P));
-        COLA_HIP(h, gram(fp, fp, P, Q, Gpi));
+        COLA_TRY(apply_op(h, T, P, COLA_OP_SCHUR, 0, prec, n, c.st));
+        COLA_HIP(h, launch_gram(S, n, fp, fp, T, T, red(Gpi), c.st));
+        COLA_TRY(apply_op(h, Q, T, COLA_OP_SCHUR_DAG, 0, prec, n, c.st));
         COLA_HIP(h, launch_block_solve(Gpi, Grho[cur], mask_bits, n, alpha, c.st));
-        COLA_HIP(h, launch_block_axpy(S, n, fx, fp, x32, P, r32, Q, alpha, c.st));
+        const Reduce rr = red(Grho[1 - cur]);
+        COLA_HIP(h, launch_block_axpy(S, n, fx, fp, x32, P, r32, Q, alpha, &rr, c.st));
         ++it;
-        COLA_HIP(h, gram(fx, fx, r32, r32, Grho[1 - cur]));
         if (it % check == 0 || it == max_it) {
             COLA_HIP(h, hipMemcpyAsync(host.data(), Grho[1 - cur], sizeof(double) * host.size(),
                                        hipMemcpyDeviceToHost, c.st));
@@ -465,8 +478,11 @@ int solve_defect(const Ctx &c, int inner_prec, const cola_cg_params_t &p, void *
                  const void *b64, const std::vector<double> &thr, Outcome *o) {
     cola_handle_t *h = c.h;
     const BlasShape sh = c.shape();
-    const int check = p.check_interval > 0 ? p.check_interval : 8;
-    const double itol = p.inner_tol > 0 ? p.inner_tol : (inner_prec == COLA_FP16 ? 1e-2 : 1e-4);
+    const int check = p.check_interval > 0 ? p.check_interval : default_check(c, 8);
+    // default inner reductions: about as deep as the inner storage keeps the iterated
+    // residual honest (FP16 ~5e-4 per rounding, FP32 ~6e-8), so that few restarts throw
+    // away Krylov spaces: FP16 1e-2, FP32 1e-5 (two cycles for a 1e-10 solve)
+    const double itol = p.inner_tol > 0 ? p.inner_tol : (inner_prec == COLA_FP16 ? 1e-2 : 1e-5);
     void *r64, *x32, *r32;
     COLA_TRY(vec(c, "r64", SpinorFmt::F64, &r64));
     COLA_TRY(vec(c, "x32", SpinorFmt::F32, &x32));
