@@ -9,6 +9,10 @@
 // the mixing needs come from LDS, where each lane put its own element of the unit (two
 // buffers, alternating between units, so one barrier per unit suffices).  Small matrices
 // are complex FP64, row-major, in device memory.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "device.h"
 #include "launch.h"
 
@@ -288,12 +292,32 @@ __global__ void __launch_bounds__(64) block_solve_kernel(const double *Hg, const
     }
 }
 
-// Blocks for a unit kernel: a grid-stride loop over 12 S / 16 units; the reducing kernels
-// stay within the Gram partial rows.
-int unit_grid(int S, bool reduce) {
+// Blocks for a unit kernel (a grid-stride loop over the 12 S / 16 units): as many as are
+// resident on the device at once, so that every block takes an equal share of the units
+// and no second, partly filled round of blocks trails the first; the reducing kernels
+// stay within the Gram partial rows.  Occupancies are cached per (kernel, block, LDS).
+int unit_grid(const void *kernel, int block, size_t shm, int S, int ncu, bool reduce) {
+    static std::mutex mu;
+    static std::map<std::tuple<const void *, int, size_t>, int> occ_cache;
+    int occ = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        const auto key = std::make_tuple(kernel, block, shm);
+        auto it = occ_cache.find(key);
+        if (it != occ_cache.end()) {
+            occ = it->second;
+        } else {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, block, shm) !=
+                hipSuccess)
+                occ = 1;
+            occ_cache[key] = occ;
+        }
+    }
     const size_t units = (size_t)12 * (S / kUnitSites);
-    const size_t cap = reduce ? kGramMaxBlocks : 4096;
-    return (int)(units < cap ? (units < 1 ? 1 : units) : cap);
+    size_t g = (size_t)(occ < 1 ? 1 : occ) * (size_t)(ncu < 1 ? 1 : ncu);
+    if (reduce && g > (size_t)kGramMaxBlocks) g = kGramMaxBlocks;
+    if (g > units) g = units;
+    return (int)(g < 1 ? 1 : g);
 }
 
 }  // namespace
@@ -302,15 +326,17 @@ int unit_grid(int S, bool reduce) {
     M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16)
 
 template <SpinorFmt FA, SpinorFmt FB>
-hipError_t gram_n(int S, int n, const void *A, const void *B, const Reduce &red, hipStream_t st) {
+hipError_t gram_n(int S, int n, int ncu, const void *A, const void *B, const Reduce &red,
+                  hipStream_t st) {
     const size_t shm = (size_t)4 * 2 * n * n * sizeof(double);
-    const int grid = unit_grid(S, true);
     switch (n) {
 #define CASE(K)                                                                               \
-    case K:                                                                                   \
+    case K: {                                                                                 \
+        const int grid = unit_grid((const void *)gram_kernel<FA, FB, K>, kUnitSites * K, shm,  \
+                                   S, ncu, true);                                             \
         hipLaunchKernelGGL((gram_kernel<FA, FB, K>), dim3(grid), dim3(kUnitSites * K), shm, st, \
                            A, B, S, red);                                                     \
-        break;
+    } break;
         COLA_BLOCK_N(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -318,32 +344,39 @@ hipError_t gram_n(int S, int n, const void *A, const void *B, const Reduce &red,
     return hipGetLastError();
 }
 
-hipError_t launch_gram(int S, int n, SpinorFmt fa, SpinorFmt fb, const void *A, const void *B,
-                       const Reduce &red, hipStream_t st) {
+hipError_t launch_gram(int S, int n, int ncu, SpinorFmt fa, SpinorFmt fb, const void *A,
+                       const void *B, const Reduce &red, hipStream_t st) {
     if (n < 1 || n > kMaxN || fa != fb || S % kUnitSites) return hipErrorInvalidValue;
     switch (fa) {
-        case SpinorFmt::F64: return gram_n<SpinorFmt::F64, SpinorFmt::F64>(S, n, A, B, red, st);
-        case SpinorFmt::F32: return gram_n<SpinorFmt::F32, SpinorFmt::F32>(S, n, A, B, red, st);
-        case SpinorFmt::F16: return gram_n<SpinorFmt::F16, SpinorFmt::F16>(S, n, A, B, red, st);
+        case SpinorFmt::F64:
+            return gram_n<SpinorFmt::F64, SpinorFmt::F64>(S, n, ncu, A, B, red, st);
+        case SpinorFmt::F32:
+            return gram_n<SpinorFmt::F32, SpinorFmt::F32>(S, n, ncu, A, B, red, st);
+        case SpinorFmt::F16:
+            return gram_n<SpinorFmt::F16, SpinorFmt::F16>(S, n, ncu, A, B, red, st);
     }
     return hipErrorInvalidValue;
 }
 
 template <SpinorFmt FX, SpinorFmt FP>
-hipError_t axpy_n(int S, int n, void *X, const void *P, void *R, const void *Q,
+hipError_t axpy_n(int S, int n, int ncu, void *X, const void *P, void *R, const void *Q,
                   const double *alpha, const Reduce *gram, hipStream_t st) {
     const Reduce red = gram ? *gram : Reduce{nullptr, nullptr, nullptr};
-    const int grid = unit_grid(S, gram != nullptr);
     const size_t shm = gram ? (size_t)4 * 2 * n * n * sizeof(double) : 0;
     switch (n) {
 #define CASE(K)                                                                               \
     case K:                                                                                   \
-        if (gram)                                                                             \
+        if (gram) {                                                                           \
+            const int grid = unit_grid((const void *)block_axpy_kernel<FX, FP, K, true>,      \
+                                       kUnitSites * K, shm, S, ncu, true);                    \
             hipLaunchKernelGGL((block_axpy_kernel<FX, FP, K, true>), dim3(grid),              \
                                dim3(kUnitSites * K), shm, st, X, P, R, Q, alpha, S, red);     \
-        else                                                                                  \
+        } else {                                                                              \
+            const int grid = unit_grid((const void *)block_axpy_kernel<FX, FP, K, false>,     \
+                                       kUnitSites * K, 0, S, ncu, false);                     \
             hipLaunchKernelGGL((block_axpy_kernel<FX, FP, K, false>), dim3(grid),             \
                                dim3(kUnitSites * K), 0, st, X, P, R, Q, alpha, S, red);       \
+        }                                                                                     \
         break;
         COLA_BLOCK_N(CASE)
 #undef CASE
@@ -352,16 +385,16 @@ hipError_t axpy_n(int S, int n, void *X, const void *P, void *R, const void *Q,
     return hipGetLastError();
 }
 
-hipError_t launch_block_axpy(int S, int n, SpinorFmt fx, SpinorFmt fp, void *X, const void *P,
-                             void *R, const void *Q, const double *alpha, const Reduce *gram,
-                             hipStream_t st) {
+hipError_t launch_block_axpy(int S, int n, int ncu, SpinorFmt fx, SpinorFmt fp, void *X,
+                             const void *P, void *R, const void *Q, const double *alpha,
+                             const Reduce *gram, hipStream_t st) {
     if (n < 1 || n > kMaxN || S % kUnitSites) return hipErrorInvalidValue;
     if (fx == SpinorFmt::F32 && fp == SpinorFmt::F16)
-        return axpy_n<SpinorFmt::F32, SpinorFmt::F16>(S, n, X, P, R, Q, alpha, gram, st);
+        return axpy_n<SpinorFmt::F32, SpinorFmt::F16>(S, n, ncu, X, P, R, Q, alpha, gram, st);
     if (fx == SpinorFmt::F32 && fp == SpinorFmt::F32)
-        return axpy_n<SpinorFmt::F32, SpinorFmt::F32>(S, n, X, P, R, Q, alpha, gram, st);
+        return axpy_n<SpinorFmt::F32, SpinorFmt::F32>(S, n, ncu, X, P, R, Q, alpha, gram, st);
     if (fx == SpinorFmt::F64 && fp == SpinorFmt::F64)
-        return axpy_n<SpinorFmt::F64, SpinorFmt::F64>(S, n, X, P, R, Q, alpha, gram, st);
+        return axpy_n<SpinorFmt::F64, SpinorFmt::F64>(S, n, ncu, X, P, R, Q, alpha, gram, st);
     return hipErrorInvalidValue;
 }
 
@@ -373,15 +406,16 @@ hipError_t launch_block_solve(const double *H, const double *B, unsigned act, in
 }
 
 template <SpinorFmt FR, SpinorFmt FP>
-hipError_t xpay_n(int S, int n, void *Pn, const void *R, const void *P, const double *beta,
-                  hipStream_t st) {
-    const int grid = unit_grid(S, false);
+hipError_t xpay_n(int S, int n, int ncu, void *Pn, const void *R, const void *P,
+                  const double *beta, hipStream_t st) {
     switch (n) {
 #define CASE(K)                                                                                \
-    case K:                                                                                    \
+    case K: {                                                                                  \
+        const int grid = unit_grid((const void *)block_xpay_kernel<FR, FP, K>, kUnitSites * K,  \
+                                   0, S, ncu, false);                                          \
         hipLaunchKernelGGL((block_xpay_kernel<FR, FP, K>), dim3(grid), dim3(kUnitSites * K), 0, \
                            st, Pn, R, P, beta, S);                                             \
-        break;
+    } break;
         COLA_BLOCK_N(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -389,8 +423,8 @@ hipError_t xpay_n(int S, int n, void *Pn, const void *R, const void *P, const do
     return hipGetLastError();
 }
 
-hipError_t launch_block_xpay(int S, int n, SpinorFmt fr, SpinorFmt fp, void *Pn, const void *R,
-                             const void *P, const double *beta, hipStream_t st) {
+hipError_t launch_block_xpay(int S, int n, int ncu, SpinorFmt fr, SpinorFmt fp, void *Pn,
+                             const void *R, const void *P, const double *beta, hipStream_t st) {
     if (n < 1 || n > kMaxN) return hipErrorInvalidValue;
     if (fr == SpinorFmt::F32 && fp == SpinorFmt::F16) {
         size_t grid = ((size_t)S * n + 255) / 256;
@@ -400,9 +434,9 @@ hipError_t launch_block_xpay(int S, int n, SpinorFmt fr, SpinorFmt fp, void *Pn,
         return hipGetLastError();
     }
     if (fr == SpinorFmt::F32 && fp == SpinorFmt::F32)
-        return xpay_n<SpinorFmt::F32, SpinorFmt::F32>(S, n, Pn, R, P, beta, st);
+        return xpay_n<SpinorFmt::F32, SpinorFmt::F32>(S, n, ncu, Pn, R, P, beta, st);
     if (fr == SpinorFmt::F64 && fp == SpinorFmt::F64)
-        return xpay_n<SpinorFmt::F64, SpinorFmt::F64>(S, n, Pn, R, P, beta, st);
+        return xpay_n<SpinorFmt::F64, SpinorFmt::F64>(S, n, ncu, Pn, R, P, beta, st);
     return hipErrorInvalidValue;
 }
 

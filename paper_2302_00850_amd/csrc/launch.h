@@ -82,22 +82,23 @@ hipError_t launch_residual(const BlasShape &b, void *r, const void *bb, const vo
 hipError_t launch_clover_site(const BlasShape &b, SpinorFmt f, int clov_double, void *out,
                               const void *in, const void *clov, int parity, hipStream_t st);
 
-// --- block CG on n <= 16 rhs of one packed block (stride S)
+// --- block CG on n <= 16 rhs of one packed block (stride S; ncu: compute units of the
+// device, for the resident grid of the grid-stride kernels)
 // red.result receives G transposed: (b * n + a) * 2 + {re, im} = sum conj(A_a) B_b
-hipError_t launch_gram(int S, int n, SpinorFmt fa, SpinorFmt fb, const void *A, const void *B,
-                       const Reduce &red, hipStream_t st);
+hipError_t launch_gram(int S, int n, int ncu, SpinorFmt fa, SpinorFmt fb, const void *A,
+                       const void *B, const Reduce &red, hipStream_t st);
 // X_b += sum_a P_a alpha_ab, R_b -= sum_a Q_a alpha_ab (alpha row-major complex FP64);
 // with gram, also the Gram matrix R^H R of the updated R into gram->result (as launch_gram)
-hipError_t launch_block_axpy(int S, int n, SpinorFmt fx, SpinorFmt fp, void *X, const void *P,
-                             void *R, const void *Q, const double *alpha, const Reduce *gram,
-                             hipStream_t st);
+hipError_t launch_block_axpy(int S, int n, int ncu, SpinorFmt fx, SpinorFmt fp, void *X,
+                             const void *P, void *R, const void *Q, const double *alpha,
+                             const Reduce *gram, hipStream_t st);
 // Z = H^-1 B over the active columns (bit mask act), H and B Gram results (transposed
 // layout), pivots below 1e-13 of the largest diagonal deflated; Z row-major (one thread)
 hipError_t launch_block_solve(const double *H, const double *B, unsigned act, int n, double *Z,
                               hipStream_t st);
 // Pn_b = R_b + sum_a P_a beta_ab
-hipError_t launch_block_xpay(int S, int n, SpinorFmt fr, SpinorFmt fp, void *Pn, const void *R,
-                             const void *P, const double *beta, hipStream_t st);
+hipError_t launch_block_xpay(int S, int n, int ncu, SpinorFmt fr, SpinorFmt fp, void *Pn,
+                             const void *R, const void *P, const double *beta, hipStream_t st);
 
 // --- low-eigenmode solver: one-rhs FP64 packed fields as flat arrays of n complex values
 constexpr int kEigChunk = 8;        // vectors per dot / linear-combination launch

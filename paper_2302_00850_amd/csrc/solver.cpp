@@ -439,15 +439,16 @@ int inner_block_cg(const Ctx &c, int prec, void *x32, void *r32,
     COLA_HIP(h, launch_convert(sh, fp, fx, P, r32, nullptr, 0, nullptr, c.st));
     auto red = [&](double *out) { return Reduce{h->partial, h->counter, out}; };
     int cur = 0;
-    COLA_HIP(h, launch_gram(S, n, fx, fx, r32, r32, red(Grho[cur]), c.st));
+    COLA_HIP(h, launch_gram(S, n, h->num_cu, fx, fx, r32, r32, red(Grho[cur]), c.st));
     int it = 0;
     while (it < max_it) {
         COLA_TRY(apply_op(h, T, P, COLA_OP_SCHUR, 0, prec, n, c.st));
-        COLA_HIP(h, launch_gram(S, n, fp, fp, T, T, red(Gpi), c.st));
+        COLA_HIP(h, launch_gram(S, n, h->num_cu, fp, fp, T, T, red(Gpi), c.st));
         COLA_TRY(apply_op(h, Q, T, COLA_OP_SCHUR_DAG, 0, prec, n, c.st));
         COLA_HIP(h, launch_block_solve(Gpi, Grho[cur], mask_bits, n, alpha, c.st));
         const Reduce rr = red(Grho[1 - cur]);
-        COLA_HIP(h, launch_block_axpy(S, n, fx, fp, x32, P, r32, Q, alpha, &rr, c.st));
+        COLA_HIP(h, launch_block_axpy(S, n, h->num_cu, fx, fp, x32, P, r32, Q, alpha, &rr,
+                                      c.st));
         ++it;
         if (it % check == 0 || it == max_it) {
             COLA_HIP(h, hipMemcpyAsync(host.data(), Grho[1 - cur], sizeof(double) * host.size(),
@@ -466,7 +467,7 @@ int inner_block_cg(const Ctx &c, int prec, void *x32, void *r32,
             if (!any) break;
         }
         COLA_HIP(h, launch_block_solve(Grho[cur], Grho[1 - cur], mask_bits, n, beta, c.st));
-        COLA_HIP(h, launch_block_xpay(S, n, fx, fp, Pn, r32, P, beta, c.st));
+        COLA_HIP(h, launch_block_xpay(S, n, h->num_cu, fx, fp, Pn, r32, P, beta, c.st));
         std::swap(P, Pn);
         cur = 1 - cur;
     }
