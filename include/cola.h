@@ -116,7 +116,9 @@ typedef struct {
                               solver of the DEFECT schemes on the SCHUR and PROPAGATOR
                               systems (COLA_EINVAL otherwise)                          */
     double tol;            /* stop when ||b - A x|| / ||b|| <= tol for every column,
-                              A the system's operator, checked in FP64                   */
+                              A the system's operator (M for PROPAGATOR, whose normal
+                              equations are tightened per column until the full-lattice
+                              residual meets tol), checked in FP64                      */
     int max_iter;          /* cap on (inner) iterations, summed over outer cycles       */
     int reliable_interval; /* FP32_RELIABLE: iterations between FP64 residual updates   */
     double inner_tol;      /* DEFECT: relative residual reduction of each inner solve

@@ -868,29 +868,59 @@ __device__ __forceinline__ void stage_clover_pair(const void *clov, int S, int p
 // ---------------------------------------------------------------- reduction
 
 // Per-block part of a two-kernel reduction: the lanes' values v[0..n) for columns q0..
-// of slot `slot` are summed over the block (LDS tree over the T slots of red, which holds
-// T * width doubles) into partial[q * nblocks + bid] (column-major, so the reduction
-// reads each column contiguously).  A following reduce_partials launch adds the blocks'
+// q0 + n are summed over the block into partial[q * nblocks + bid] (column-major, so the
+// reduction reads each column contiguously).  Lane t owns columns (t mod g) n .. + n,
+// g = width / n (the callers' layout: slot t / g, q0 = (t mod g) n), so lanes t and
+// t + g m share columns.  Within a wavefront those lanes are summed by shuffles (an xor
+// butterfly when g is a power of two and the wavefront is whole, else a chain in lane
+// order), then the wavefronts' sums in wavefront order through LDS (red holds T * width
+// doubles, T = blockDim / g).  A following reduce_partials launch adds the blocks'
 // partials in block order; the kernel boundary orders the writes, so blocks need no
 // fence or ticket (device-scope fences write back the XCD's L2 on this chip: with tens
-// of thousands of blocks they cost more than the kernel).
+// of thousands of blocks they cost more than the kernel).  Every sum has a fixed order.
 template <int NV>
 __device__ void block_sum_to_partial(double *red, int T, int width, int slot, int q0, int n,
                                      const double (&v)[NV], double *partial, uint32_t bid,
                                      uint32_t nblocks) {
+    (void)T;
+    (void)slot;
+    (void)q0;
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
-    for (int k = tid; k < T * width; k += nt) red[k] = 0.0;
-    __syncthreads();
+    const int g = width / n;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = (nt + 63) >> 6;
+    const int live = min(64, nt - 64 * wave);  // lanes of this wavefront
+    double s[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k)  // constant indices keep v in registers
-        if (k < n) red[slot * width + q0 + k] = v[k];
-    __syncthreads();
-    for (int w = T >> 1; w > 0; w >>= 1) {
-        for (int k = tid; k < w * width; k += nt) red[k] += red[k + w * width];
-        __syncthreads();
+    for (int k = 0; k < NV; ++k) s[k] = v[k];
+    if ((g & (g - 1)) == 0 && live == 64) {
+        for (int off = 32; off >= g; off >>= 1) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) s[k] += __shfl_xor(s[k], off);
+        }
+    } else {
+        for (int m = g; m < 64; m += g) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                const double o = __shfl(v[k], (lane + m) & 63);
+                if (lane + m < live) s[k] += o;
+            }
+        }
     }
-    for (int k = tid; k < width; k += nt) partial[(size_t)k * nblocks + bid] = red[k];
+    for (int k = tid; k < nwaves * width; k += nt) red[k] = 0.0;
+    __syncthreads();
+    if (lane < g && lane < live) {
+        const int j = tid % g;
+#pragma unroll
+        for (int k = 0; k < NV; ++k)  // constant indices keep s in registers
+            if (k < n) red[wave * width + j * n + k] = s[k];
+    }
+    __syncthreads();
+    for (int q = tid; q < width; q += nt) {
+        double a = red[q];
+        for (int w = 1; w < nwaves; ++w) a += red[w * width + q];
+        partial[(size_t)q * nblocks + bid] = a;
+    }
 }
 
 // Deterministic per-block reduction: the lanes' values v[0..n) for columns q0.. of

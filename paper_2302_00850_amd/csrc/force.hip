@@ -37,40 +37,44 @@ __global__ void __launch_bounds__(256) force_kernel(const Geom g, const void *ga
         int y[4] = {x[0], x[1], x[2], x[3]};
         y[mu] = y[mu] + 1 == g.L[mu] ? 0 : y[mu] + 1;
         const uint32_t sf = (uint32_t)(y[0] + g.L[0] * (y[1] + g.L[1] * (y[2] + g.L[2] * y[3])));
-        C yx[12], yf[12], xx[12], xf[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            yx[c] = Y[(size_t)s * 12 + c];
-            yf[c] = Y[(size_t)sf * 12 + c];
-            xx[c] = X[(size_t)s * 12 + c];
-            xf[c] = X[(size_t)sf * 12 + c];
-        }
-        // A = (1 - g_mu) Y(x), B = (1 + g_mu) Y(x + mu)
-        C h[6], A[12], B[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) A[c] = B[c] = C{0.0, 0.0};
-        project(mu, -1.0, yx, h);
-        expand_add(mu, -1.0, h, A);
-        project(mu, 1.0, yf, h);
-        expand_add(mu, 1.0, h, B);
+        // (1 -+ g_mu) = E E^H with E^H the spin projection (E^H E = 2), so each spin sum
+        // runs over the two projected components:
+        //   sum_s ((1 - g_mu) Y(x))_s,a conj(X(x+mu)_s,b) = sum_k hY_k,a conj(hXf_k,b),
+        //   hY = project_-(Y(x)), hXf = project_-(X(x+mu)); likewise with project_+ for
+        //   X(x) and (1 + g_mu) Y(x+mu).  One spinor is loaded at a time.
         const bool bnd = x[mu] == g.L[mu] - 1;
         // 2 kappa conj(e+)
         const C f = bnd ? C{2.0 * kappa * phs[mu].x, -2.0 * kappa * phs[mu].y}
                         : C{2.0 * kappa, 0.0};
         C G[9];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 9; ++k) G[k] = C{0.0, 0.0};
+        auto load = [](const C *v, uint32_t site, C out[12]) {
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                C acc = {0.0, 0.0};
+            for (int c = 0; c < 12; ++c) out[c] = v[(size_t)site * 12 + c];
+        };
+        auto accumulate = [&](const C ha[6], const C hb[6]) {
 #pragma unroll
-                for (int sp = 0; sp < 4; ++sp) {
-                    // A_a conj(X(x+mu)_b) + X(x)_a conj(B_b)
-                    acc = cjmadd(acc, xf[sp * 3 + b], A[sp * 3 + a]);
-                    acc = cjmadd(acc, B[sp * 3 + b], xx[sp * 3 + a]);
-                }
-                G[a * 3 + b] = cmul(f, acc);
-            }
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+#pragma unroll
+                    for (int k = 0; k < 2; ++k)
+                        G[a * 3 + b] = cjmadd(G[a * 3 + b], hb[k * 3 + b], ha[k * 3 + a]);
+        };
+        C sp[12], ha[6], hb[6];
+        load(Y, s, sp);
+        project(mu, -1.0, sp, ha);
+        load(X, sf, sp);
+        project(mu, -1.0, sp, hb);
+        accumulate(ha, hb);
+        load(X, s, sp);
+        project(mu, 1.0, sp, ha);
+        load(Y, sf, sp);
+        project(mu, 1.0, sp, hb);
+        accumulate(ha, hb);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) G[k] = cmul(f, G[k]);
         C *out = F + (size_t)t * 9;
         if (mode == 0) {
 #pragma unroll

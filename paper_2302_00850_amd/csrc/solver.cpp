@@ -621,61 +621,94 @@ int cg_solve_impl(cola_handle_t *h, void *x, const void *b, int nrhs, const cola
     for (int q = 0; q < nrhs; ++q) thr[q] = p->tol * p->tol * bn[q];
 
     Outcome o;
-    switch (p->scheme) {
-        case COLA_CG_FP64: COLA_TRY(solve_reliable(c, COLA_FP64, *p, x64, b64, thr, &o)); break;
-        case COLA_CG_FP32_RELIABLE:
-            COLA_TRY(solve_reliable(c, COLA_FP32, *p, x64, b64, thr, &o));
-            break;
-        case COLA_CG_FP16_DEFECT: COLA_TRY(solve_defect(c, COLA_FP16, *p, x64, b64, thr, &o)); break;
-        case COLA_CG_FP32_DEFECT: COLA_TRY(solve_defect(c, COLA_FP32, *p, x64, b64, thr, &o)); break;
-        default: return set_error(h, COLA_EINVAL, "unknown solver scheme");
-    }
-
+    cola_cg_params_t pp = *p;
+    auto run = [&]() -> int {
+        o.final_tr.clear();
+        switch (pp.scheme) {
+            case COLA_CG_FP64: return solve_reliable(c, COLA_FP64, pp, x64, b64, thr, &o);
+            case COLA_CG_FP32_RELIABLE: return solve_reliable(c, COLA_FP32, pp, x64, b64, thr, &o);
+            case COLA_CG_FP16_DEFECT: return solve_defect(c, COLA_FP16, pp, x64, b64, thr, &o);
+            case COLA_CG_FP32_DEFECT: return solve_defect(c, COLA_FP32, pp, x64, b64, thr, &o);
+            default: return set_error(h, COLA_EINVAL, "unknown solver scheme");
+        }
+    };
     // final FP64 true residual of the solved system (the solver's last one when it
     // computed it for the returned x)
     std::vector<double> tr(nrhs);
-    if ((int)o.final_tr.size() == nrhs) {
-        tr = o.final_tr;
-    } else {
-        void *r64;
-        COLA_TRY(vec(c, "r64", SpinorFmt::F64, &r64));
-        COLA_TRY(true_residual(c, r64, b64, x64, TRUE_RES));
-        COLA_TRY(read_slot(c, TRUE_RES, tr.data()));
-    }
-    for (int q = 0; q < nrhs; ++q)
-        if (!(tr[q] <= thr[q]) && o.status == COLA_OK) o.status = COLA_NOT_CONVERGED;
+    auto system_residual = [&]() -> int {
+        if ((int)o.final_tr.size() == nrhs) {
+            tr = o.final_tr;
+        } else {
+            void *r64;
+            COLA_TRY(vec(c, "r64", SpinorFmt::F64, &r64));
+            COLA_TRY(true_residual(c, r64, b64, x64, TRUE_RES));
+            COLA_TRY(read_slot(c, TRUE_RES, tr.data()));
+        }
+        for (int q = 0; q < nrhs; ++q)
+            if (!(tr[q] <= thr[q]) && o.status == COLA_OK) o.status = COLA_NOT_CONVERGED;
+        return COLA_OK;
+    };
+    COLA_TRY(run());
+    COLA_TRY(system_residual());
 
     if (p->system == COLA_SYS_PROPAGATOR) {
-        // x_o = A_oo^-1 (b_o + kappa D_oe x_e); residual of M x = b on the full lattice,
-        // one parity block at a time in the solver's FP64 residual block:
-        // t = A_pp x_p - kappa D x_{1-p}, then t = b_p - t
+        // x_o = A_oo^-1 (b_o + kappa D_oe x_e) and the residual of M x = b on the full
+        // lattice, one parity block at a time in the solver's FP64 residual block:
+        // t = A_pp x_p - kappa D x_{1-p}, then t = b_p - t.  With x_o reconstructed
+        // exactly, b - M x is (b_hat - S x_e) on the even sites and zero on the odd ones,
+        // which the normal equations bound only up to the condition of S: a column whose
+        // full residual misses tol has its normal-system threshold cut by
+        // (tol / residual / 2)^2 and the solve continues from x (at most three times).
         void *xfull, *t;
         COLA_TRY(get_vec(h, "prop_x_full_" + std::to_string(nrhs), 2 * bb64, &xfull));
         COLA_TRY(vec(c, "r64", SpinorFmt::F64, &t));
-        COLA_HIP(h, hipMemcpyAsync(xfull, x64, bb64, hipMemcpyDeviceToDevice, st));
-        HopCall hc{(char *)xfull + bb64, x64, 1, 0};
-        hc.epi = clover ? EPI_XPAY_CLOV : EPI_XPAY;
-        hc.x = (const char *)bfull + bb64;
-        hc.a = h->kappa;
-        hc.clov = h->clovinv64;
-        COLA_TRY(hop(h, hc, COLA_FP64, nrhs, st));
+        std::vector<double> bf(nrhs);
         const BlasShape sh1 = blas_shape(h->g, nrhs, 1);
-        for (int q = 0; q < 2; ++q) {
-            HopCall hm{t, (const char *)xfull + (1 - q) * bb64, q, 0};
-            hm.epi = clover ? EPI_CLOV_XPAY : EPI_XPAY;
-            hm.x = (const char *)xfull + q * bb64;
-            hm.a = -h->kappa;
-            hm.clov = h->clov64;
-            COLA_TRY(hop(h, hm, COLA_FP64, nrhs, st));
-            COLA_HIP(h, launch_residual(sh1, t, (const char *)bfull + q * bb64, t,
-                                        reduce_into(h, q == 0 ? TRUE_RES : TMP), st));
-        }
-        COLA_HIP(h, launch_scalar_add(c.slot(TRUE_RES), c.slot(TMP), nrhs, st));
-        const Reduce red_bf = reduce_into(h, BNORM);
         const BlasShape shf = blas_shape(h->g, nrhs, 2);
+        const Reduce red_bf = reduce_into(h, BNORM);
         COLA_HIP(h, launch_norm2(shf, SpinorFmt::F64, bfull, red_bf, st));
-        COLA_TRY(read_slot(c, TRUE_RES, tr.data()));
-        COLA_TRY(read_slot(c, BNORM, bn.data()));
+        COLA_TRY(read_slot(c, BNORM, bf.data()));
+        auto full_residual = [&]() -> int {
+            COLA_HIP(h, hipMemcpyAsync(xfull, x64, bb64, hipMemcpyDeviceToDevice, st));
+            HopCall hc{(char *)xfull + bb64, x64, 1, 0};
+            hc.epi = clover ? EPI_XPAY_CLOV : EPI_XPAY;
+            hc.x = (const char *)bfull + bb64;
+            hc.a = h->kappa;
+            hc.clov = h->clovinv64;
+            COLA_TRY(hop(h, hc, COLA_FP64, nrhs, st));
+            for (int q = 0; q < 2; ++q) {
+                HopCall hm{t, (const char *)xfull + (1 - q) * bb64, q, 0};
+                hm.epi = clover ? EPI_CLOV_XPAY : EPI_XPAY;
+                hm.x = (const char *)xfull + q * bb64;
+                hm.a = -h->kappa;
+                hm.clov = h->clov64;
+                COLA_TRY(hop(h, hm, COLA_FP64, nrhs, st));
+                COLA_HIP(h, launch_residual(sh1, t, (const char *)bfull + q * bb64, t,
+                                            reduce_into(h, q == 0 ? TRUE_RES : TMP), st));
+            }
+            COLA_HIP(h, launch_scalar_add(c.slot(TRUE_RES), c.slot(TMP), nrhs, st));
+            return read_slot(c, TRUE_RES, tr.data());
+        };
+        COLA_TRY(full_residual());
+        for (int round = 0; round < 3 && o.status == COLA_OK; ++round) {
+            bool again = false;
+            for (int q = 0; q < nrhs; ++q) {
+                const double lim = p->tol * p->tol * bf[q];
+                if (tr[q] > lim) {
+                    thr[q] *= 0.25 * lim / tr[q];
+                    again = true;
+                }
+            }
+            if (!again) break;
+            pp.use_x0 = 1;
+            COLA_TRY(run());
+            COLA_TRY(system_residual());
+            COLA_TRY(full_residual());
+        }
+        for (int q = 0; q < nrhs; ++q)
+            if (!(tr[q] <= p->tol * p->tol * bf[q]) && o.status == COLA_OK)
+                o.status = COLA_NOT_CONVERGED;
+        bn = bf;
         COLA_HIP(h, launch_unpack_spinor(h->g, SpinorFmt::F64, x, xfull, nrhs, -1, st));
     } else if (p->system == COLA_SYS_SCHUR) {
         COLA_HIP(h, hipMemsetAsync(x, 0, (size_t)h->g.Vh * 2 * 12 * 16 * nrhs, st));

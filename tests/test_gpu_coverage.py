@@ -225,7 +225,9 @@ def test_c5_propagator_fp32_defect_sampled_residual():
     lat.close()
     sites = _check_sites(C5, 192, 6)
     worst = _propagator_site_residuals(Uh, x, b, C5, kappa, csw, sites)
-    assert worst <= 1e-8, worst
+    # a site's share of |M x - b| is at most the whole, which meets the tolerance
+    assert worst <= 1.1e-10, worst
+    assert max(info["true_rel_residual"]) <= 1e-10, info
     # the solution is not trivially small where the residual is checked
     assert float(torch.linalg.vector_norm(x[0].reshape(-1, 12)[0])) > 0.5
 
@@ -246,7 +248,8 @@ def test_block_cg_c3_propagator_sampled_residual():
                      tol=1e-10, block=1)
     assert info["status"] == cola.COLA_OK, info
     sites = _check_sites(dims, 192, 7)
-    assert _propagator_site_residuals(Uh, x, b, dims, kappa, 0.0, sites) <= 1e-8
+    assert _propagator_site_residuals(Uh, x, b, dims, kappa, 0.0, sites) <= 1.1e-10
+    assert max(info["true_rel_residual"]) <= 1e-10, info
     x2, info2 = lat.cg(b, system=cola.COLA_SYS_PROPAGATOR, scheme=cola.COLA_CG_FP16_DEFECT,
                        tol=1e-10, block=0)
     assert info2["status"] == cola.COLA_OK
@@ -299,6 +302,6 @@ def test_tuner_bitwise_and_tuned_solve(prec, tmp_path):
     assert info["status"] == cola.COLA_OK, info
     xs = x.cpu().numpy()
     for q in (0, 4, 11):
-        assert rel(oracle.apply_M(U, xs[q], kappa, ANTI), b[q]) < 1e-8
+        assert rel(oracle.apply_M(U, xs[q], kappa, ANTI), b[q]) <= 1.1e-10
     tuned.close()
     lat.close()

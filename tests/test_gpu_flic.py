@@ -92,7 +92,7 @@ def test_flic_propagator_solve(fields, scheme, csw):
     xs = x.cpu().numpy()
     for q in range(2):
         r = rel(flic.apply_flic(U, F, xs[q], kappa, ANTI, csw=csw), b[q])
-        assert r < 1e-9, (q, r)
+        assert r <= 1.1e-11, (q, r)  # the full-lattice residual meets tol
 
 
 def test_flic_normal_cg_and_return_to_wilson(fields):

@@ -112,7 +112,7 @@ def test_block_cg_reaches_tolerance(fields, scheme, system):
             r = _normal_residual(U, xs[q], src[q], system, KAPPA, ANTI)
             assert r <= 1.05e-10, (q, r, info)
         else:
-            assert rel(oracle.apply_M(U, xs[q], KAPPA, ANTI), src[q]) < 1e-8
+            assert rel(oracle.apply_M(U, xs[q], KAPPA, ANTI), src[q]) <= 1.1e-10
     # lockstep twin: the same solutions (to the solver tolerance, relative to cond)
     x2, info2 = lat.cg(_cuda(src), system=system, scheme=scheme, tol=1e-10, block=0)
     assert rel(xs, x2.cpu().numpy()) < 1e-7
@@ -217,7 +217,7 @@ def test_propagator_solves_M(fields, csw):
     assert info["status"] == cola.COLA_OK, info
     xs = x.cpu().numpy()[0]
     r = rel(oracle.apply_M(U, xs, kappa, GENERIC, clover=A), b[0])
-    assert r < 1e-9
+    assert r <= 1.1e-12  # the full-lattice residual meets tol
     assert r == pytest.approx(info["true_rel_residual"][0], rel=1e-3, abs=1e-14)
 
 
