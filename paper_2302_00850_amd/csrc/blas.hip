@@ -4,6 +4,7 @@
 // register.  Consecutive lanes take consecutive (site, rhs) pairs, which in
 // the rhs-innermost packed layout are consecutive addresses for every
 // component.  Reductions are per rhs, in FP64, deterministic.
+#include "cola.h"
 #include "device.h"
 #include "launch.h"
 
@@ -325,9 +326,10 @@ struct MsFn {
     void *x, *p;
     const void *r;
     size_t bx, br;
-    MsCoef k;
+    const MsCoef *kp;
     int S, R;
     __device__ double operator()(const Loc &l) const {
+        const MsCoef &k = *kp;
         if (!k.active[l.r]) return 0.0;
         const auto X = view<SpinorFmt::F64>(x, bx, l, S, R);
         const auto P = view<SpinorFmt::F64>(p, bx, l, S, R);
@@ -380,10 +382,116 @@ __global__ void scalar_add_kernel(double *a, const double *b, int n) {
 }  // namespace
 
 hipError_t launch_ms_update(const BlasShape &sh, void *x, void *p, const void *r,
-                            const MsCoef &k, hipStream_t st) {
+                            const MsCoef *k, hipStream_t st) {
     MsFn fn{x, p, r, block_bytes(SpinorFmt::F64, sh.S, sh.R), block_bytes(SpinorFmt::F64, sh.S, 1),
             k, sh.S, sh.R};
     return run(fn, sh, nullptr, st);
+}
+
+namespace {
+
+struct MsShifts {
+    double sigma[kRedMaxWidth];
+};
+
+__global__ void ms_init_kernel(MsState *st, MsShifts sh, int nshift, double tol2,
+                               const double *bnorm) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double b2 = *bnorm;
+    st->nshift = nshift;
+    st->alpha_old = 1.0;
+    st->beta_old = 0.0;
+    st->rho = b2;
+    st->thr = tol2 * b2;
+    st->status = COLA_OK;
+    st->iterations = 0;
+    int all = 1;
+    for (int q = 0; q < kRedMaxWidth; ++q) {
+        const bool live = q < nshift;
+        st->sigma[q] = live ? sh.sigma[q] : 0.0;
+        st->zeta[q] = 1.0;
+        st->zold[q] = 1.0;
+        st->done[q] = live ? (b2 == 0.0 ? 1 : 0) : 1;
+        all &= st->done[q];
+        // the first update: p_q = b (alpha 0, zeta 1, beta 0)
+        st->coef.alpha[q] = 0.0;
+        st->coef.zeta[q] = 1.0;
+        st->coef.beta[q] = 0.0;
+        st->coef.active[q] = live ? 1 : 0;
+    }
+    st->finished = all;
+}
+
+// One iteration of the shifted recursion (the host loop it replaces ran the same
+// arithmetic in the same order):
+//   zeta_q' = zeta_q zeta_q^old alpha^old /
+//             (alpha beta^old (zeta_q^old - zeta_q) + zeta_q^old alpha^old (1 + sigma_q alpha))
+//   alpha_q = alpha zeta_q'/zeta_q, beta_q = beta (zeta_q'/zeta_q)^2; shifts done
+//   (zeta_q^2 |r|^2 <= tol^2 |b|^2) stay frozen.
+__global__ void ms_advance_kernel(MsState *st, const double *rho_new_p, const double *pi_p,
+                                  const double *pi2_p) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    MsCoef &k = st->coef;
+    if (st->finished || st->status != COLA_OK) {
+        for (int q = 0; q < kRedMaxWidth; ++q) k.active[q] = 0;
+        return;
+    }
+    const double rho = st->rho, rho_new = *rho_new_p;
+    const double pi = *pi_p + (pi2_p ? *pi2_p : 0.0);
+    const double alpha = rho / pi, beta = rho_new / rho;
+    if (!isfinite(alpha) || !isfinite(beta) || !(pi > 0.0)) {
+        st->status = COLA_BREAKDOWN;
+        for (int q = 0; q < kRedMaxWidth; ++q) k.active[q] = 0;
+        return;
+    }
+    bool bad = false;
+    for (int q = 0; q < st->nshift; ++q) {
+        k.active[q] = !st->done[q];
+        const double z = st->zeta[q], zo = st->zold[q];
+        double zn = z;
+        if (!st->done[q]) {  // done shifts are frozen (their zeta may underflow)
+            zn = z * zo * st->alpha_old /
+                 (alpha * st->beta_old * (zo - z) + zo * st->alpha_old * (1.0 + st->sigma[q] * alpha));
+            k.alpha[q] = alpha * zn / z;
+            k.zeta[q] = zn;
+            k.beta[q] = beta * (zn / z) * (zn / z);
+            bad |= !isfinite(zn);
+        }
+        st->zold[q] = z;
+        st->zeta[q] = zn;
+    }
+    if (bad) {
+        st->status = COLA_BREAKDOWN;
+        for (int q = 0; q < kRedMaxWidth; ++q) k.active[q] = 0;
+        return;
+    }
+    st->alpha_old = alpha;
+    st->beta_old = beta;
+    st->rho = rho_new;
+    st->iterations += 1;
+    int all = 1;
+    for (int q = 0; q < st->nshift; ++q) {
+        if (st->zeta[q] * st->zeta[q] * rho_new <= st->thr) st->done[q] = 1;
+        all &= st->done[q];
+    }
+    st->finished = all;
+}
+
+}  // namespace
+
+hipError_t launch_ms_init(MsState *state, const double *sigma, int nshift, double tol2,
+                          const double *bnorm, hipStream_t st) {
+    if (nshift < 1 || nshift > kRedMaxWidth) return hipErrorInvalidValue;
+    MsShifts sh{};
+    for (int q = 0; q < nshift; ++q) sh.sigma[q] = sigma[q];
+    hipLaunchKernelGGL(ms_init_kernel, dim3(1), dim3(64), 0, st, state, sh, nshift, tol2, bnorm);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_advance(MsState *state, const double *rho_new, const double *pi,
+                             const double *pi2, hipStream_t st) {
+    hipLaunchKernelGGL(ms_advance_kernel, dim3(1), dim3(64), 0, st, state, rho_new, pi, pi2);
+    return hipGetLastError();
 }
 
 hipError_t launch_ms_residual(const BlasShape &sh, const void *b, const void *ax, const void *x,

@@ -55,22 +55,34 @@ int alloc(const Eig &e, const std::string &tag, void **out) {
     return get_vec(e.h, "eig_" + tag + "_" + std::to_string(e.full), e.bytes, out);
 }
 
-// out[j] = <V_j, w>
-int dots(const Eig &e, const std::vector<const void *> &V, const void *w, std::vector<cd> &out) {
+// <V_j, w> into device result slots off + j (no wait)
+int dots_at(const Eig &e, const std::vector<const void *> &V, const void *w, size_t off) {
     const size_t m = V.size();
-    out.assign(m, cd(0, 0));
-    if (m == 0) return COLA_OK;
     for (size_t j0 = 0; j0 < m; j0 += kEigChunk) {
         const int k = (int)std::min<size_t>(kEigChunk, m - j0);
         EigVecs vv{};
         for (int j = 0; j < k; ++j) vv.v[j] = (const Cplx64 *)V[j0 + j];
-        COLA_HIP(e.h, launch_eig_dots(vv, k, w, e.n, e.h->partial, e.dres + 2 * j0, e.st));
+        COLA_HIP(e.h, launch_eig_dots(vv, k, w, e.n, e.h->partial, e.dres + 2 * (off + j0),
+                                      e.st));
     }
+    return COLA_OK;
+}
+
+// the first m result slots, after the queued launches (one wait)
+int read_dots(const Eig &e, size_t m, std::vector<cd> &out) {
+    out.assign(m, cd(0, 0));
+    if (m == 0) return COLA_OK;
     COLA_HIP(e.h, hipMemcpyAsync(e.h->host_scal, e.dres, sizeof(double) * 2 * m,
                                  hipMemcpyDeviceToHost, e.st));
     COLA_HIP(e.h, hipStreamSynchronize(e.st));
     for (size_t j = 0; j < m; ++j) out[j] = cd(e.h->host_scal[2 * j], e.h->host_scal[2 * j + 1]);
     return COLA_OK;
+}
+
+// out[j] = <V_j, w>
+int dots(const Eig &e, const std::vector<const void *> &V, const void *w, std::vector<cd> &out) {
+    COLA_TRY(dots_at(e, V, w, 0));
+    return read_dots(e, V.size(), out);
 }
 
 // out = a out + sum_j c_j V_j (a = 0: out is overwritten)
@@ -190,28 +202,37 @@ int eigensolve_impl(cola_handle_t *h, void *Xc, int nv, const cola_eig_params_t 
             double gn2 = d[0].real();
             const double g0 = std::sqrt(std::max(0.0, gn2));
             COLA_TRY(copy(e, pv, g));
+            // Host waits per step: five (the two projections, the products with z, the
+            // renormalisation, |g|^2).  Projecting q off X_0..X_{i-1} and x in one pass
+            // equals doing it one after the other, x being orthogonal to the X_j; q and z
+            // are used unnormalised, with |q| taken from the same wait as <x, z>, <q, z>.
+            std::vector<const void *> Vx(X.begin(), X.begin() + i);
+            Vx.push_back(x);
             for (int it = 0; it < inner_max; ++it) {
                 if (!(gn2 > 0.0)) break;
                 COLA_TRY(copy(e, q, pv));
-                COLA_TRY(project(e, X, i, q));
-                COLA_TRY(dots(e, {x}, q, d));
-                COLA_TRY(lincomb(e, q, cd(1, 0), {x}, {-d[0]}));
-                double qn;
-                COLA_TRY(norm(e, q, &qn));
-                if (!(qn > 0.0)) break;
-                COLA_TRY(lincomb(e, q, cd(1 / qn, 0), {}, {}));
+                COLA_TRY(dots(e, Vx, q, d));
+                for (auto &c : d) c = -c;
+                COLA_TRY(lincomb(e, q, cd(1, 0), Vx, d));
                 COLA_TRY(apply_A(e, z, q));
                 ++napply;
-                COLA_TRY(dots(e, {x, q}, z, d));
+                COLA_TRY(dots_at(e, {x, q}, z, 0));
+                COLA_TRY(dots_at(e, {q}, q, 2));
+                COLA_TRY(read_dots(e, 3, d));
+                const double qn = std::sqrt(std::max(0.0, d[2].real()));
+                if (!(qn > 0.0)) break;
+                // with q^ = q / |q|, z^ = z / |q|: <x, z^> = d0 / |q|, <q^, z^> = d1 / |q|^2
                 cd u0, u1;
-                lower_eigvec(mu, d[0], d[1].real(), &u0, &u1);
-                COLA_TRY(lincomb(e, x, u0, {q}, {u1}));
-                COLA_TRY(lincomb(e, y, u0, {z}, {u1}));
-                COLA_TRY(norm(e, x, &nx));
+                lower_eigvec(mu, d[0] / qn, d[1].real() / (qn * qn), &u0, &u1);
+                COLA_TRY(lincomb(e, x, u0, {q}, {u1 / qn}));
+                COLA_TRY(lincomb(e, y, u0, {z}, {u1 / qn}));
+                COLA_TRY(dots_at(e, {x}, x, 0));
+                COLA_TRY(dots_at(e, {x}, y, 1));
+                COLA_TRY(read_dots(e, 2, d));
+                nx = std::sqrt(std::max(0.0, d[0].real()));
                 COLA_TRY(lincomb(e, x, cd(1 / nx, 0), {}, {}));
                 COLA_TRY(lincomb(e, y, cd(1 / nx, 0), {}, {}));
-                COLA_TRY(dots(e, {x}, y, d));
-                mu = d[0].real();
+                mu = d[1].real() / (nx * nx);
                 COLA_TRY(lincomb(e, g, cd(0, 0), {y, x}, {cd(1, 0), cd(-mu, 0)}));
                 COLA_TRY(project(e, X, i, g));
                 COLA_TRY(dots(e, {g}, g, d));

@@ -48,8 +48,28 @@ struct MsCoef {
     double alpha[kRedMaxWidth], zeta[kRedMaxWidth], beta[kRedMaxWidth];
     int active[kRedMaxWidth];
 };
+// The shift recursion's state in device memory: a one-thread kernel advances it each
+// iteration from the base CG's rho', pi (+ pi2) and writes the coefficients the update
+// kernel reads, so an iteration needs no host round trip.
+struct MsState {
+    double zeta[kRedMaxWidth], zold[kRedMaxWidth], sigma[kRedMaxWidth];
+    double alpha_old, beta_old, rho, thr;
+    int done[kRedMaxWidth];
+    int nshift;
+    int status;      // COLA_OK or COLA_BREAKDOWN (non-finite recursion)
+    int finished;    // every shift done
+    int iterations;  // iterations advanced while not finished
+    MsCoef coef;     // this iteration's x_q, p_q coefficients
+};
+// state from sigma[nshift], tol^2 and |b|^2 (a device scalar); coef = the first update
+// (p_q = b)
+hipError_t launch_ms_init(MsState *state, const double *sigma, int nshift, double tol2,
+                          const double *bnorm, hipStream_t st);
+// one iteration of the recursion from the base rho' and pi (pi2 null: one block)
+hipError_t launch_ms_advance(MsState *state, const double *rho_new, const double *pi,
+                             const double *pi2, hipStream_t st);
 hipError_t launch_ms_update(const BlasShape &sh, void *x, void *p, const void *r,
-                            const MsCoef &k, hipStream_t st);
+                            const MsCoef *k, hipStream_t st);
 // result_q = |b - ax_q - sigma_q x_q|^2 (b a one-rhs field, ax and x with R = sh.R)
 hipError_t launch_ms_residual(const BlasShape &sh, const void *b, const void *ax, const void *x,
                               const double *sigma, const Reduce &red, hipStream_t st);

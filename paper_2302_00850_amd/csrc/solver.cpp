@@ -21,6 +21,7 @@
 //                 residual by less than 2x switch an FP16 inner solve to FP32.
 #include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -765,11 +766,16 @@ int cg_multishift_impl(cola_handle_t *h, void *x, const void *b, int nshift, con
     COLA_HIP(h, hipMemsetAsync(xb, 0, b1, st));
     COLA_HIP(h, hipMemsetAsync(xs, 0, bn_, st));
     COLA_HIP(h, hipMemsetAsync(ps, 0, bn_, st));
-    // p_q = b: the update with alpha = 0, zeta = 1, beta = 0
-    MsCoef k{};
-    for (int q = 0; q < nshift; ++q) k.zeta[q] = 1.0, k.active[q] = 1;
-    COLA_HIP(h, launch_ms_update(shn, xs, ps, r64, k, st));
+    // the shift recursion lives on the device (MsState): init writes the first update's
+    // coefficients (p_q = b); each iteration's advance kernel reads the base CG's rho'
+    // and pi where the reductions left them.  The host only reads the state's flags at
+    // the convergence checks.
+    void *state_v;
+    COLA_TRY(get_vec(h, "ms_state", sizeof(MsState), &state_v));
+    MsState *state = (MsState *)state_v;
     COLA_HIP(h, launch_norm2(sh1, SpinorFmt::F64, b64, reduce_into(h, BNORM), st));
+    COLA_HIP(h, launch_ms_init(state, sigma, nshift, p->tol * p->tol, c.slot(BNORM), st));
+    COLA_HIP(h, launch_ms_update(shn, xs, ps, r64, &state->coef, st));
     double bnorm = 0.0;
     COLA_TRY(read_slot(c, BNORM, &bnorm));
     COLA_HIP(h, hipMemcpyAsync(c.slot(RHO), c.slot(BNORM), sizeof(double),
@@ -777,16 +783,15 @@ int cg_multishift_impl(cola_handle_t *h, void *x, const void *b, int nshift, con
     if (full) COLA_TRY(zero_pi2(c));
     COLA_TRY(write_active(c, std::vector<int>{1}));
     const double thr = p->tol * p->tol * bnorm;
-    std::vector<double> zeta(nshift, 1.0), zold(nshift, 1.0), zn(nshift);
-    std::vector<int> done(nshift, bnorm == 0.0 ? 1 : 0);
-    double alpha_old = 1.0, beta_old = 0.0, rho = bnorm;
-    int status = COLA_OK, it = 0;
-    auto all_done = [&] {
-        for (int q = 0; q < nshift; ++q)
-            if (!done[q]) return false;
-        return true;
-    };
-    while (!all_done()) {
+    const int check = p->check_interval > 0 ? p->check_interval : default_check(c, 8);
+    int status = COLA_OK, it = 0, iters = 0;
+    // flags read back from the state: finished, status, iterations (consecutive ints)
+    static_assert(offsetof(MsState, status) + sizeof(int) == offsetof(MsState, finished) &&
+                      offsetof(MsState, finished) + sizeof(int) == offsetof(MsState, iterations),
+                  "state flag order");
+    bool finished = bnorm == 0.0;
+    int flags[3] = {COLA_OK, finished ? 1 : 0, 0};
+    while (!finished) {
         if (it >= p->max_iter) {
             status = COLA_NOT_CONVERGED;
             break;
@@ -796,45 +801,26 @@ int cg_multishift_impl(cola_handle_t *h, void *x, const void *b, int nshift, con
                                  SpinorFmt::F64, xb, p64, r64, ap, c.slot(RHO), c.slot(PI),
                                  full ? c.slot(PI2) : nullptr, h->active,
                                  reduce_into(h, RHO_NEW), st));
-        // RHO_NEW, PI and PI2 are consecutive slots: one read-back per iteration
-        static_assert(PI == RHO_NEW + 1 && PI2 == RHO_NEW + 2, "slot order");
-        double sl[3 * kMaxRhs];
-        COLA_HIP(h, hipMemcpyAsync(sl, c.slot(RHO_NEW), sizeof sl, hipMemcpyDeviceToHost, st));
-        COLA_HIP(h, hipStreamSynchronize(st));
-        const double rho_new = sl[0], pi = sl[kMaxRhs], pi2 = full ? sl[2 * kMaxRhs] : 0.0;
-        const double alpha = rho / (pi + pi2), beta = rho_new / rho;
-        if (!std::isfinite(alpha) || !std::isfinite(beta) || !(pi + pi2 > 0.0)) {
-            status = COLA_BREAKDOWN;
-            break;
-        }
-        for (int q = 0; q < nshift; ++q) {
-            k.active[q] = !done[q];
-            if (done[q]) {  // frozen (its zeta may underflow from here on)
-                zn[q] = zeta[q];
-                continue;
-            }
-            zn[q] = zeta[q] * zold[q] * alpha_old /
-                    (alpha * beta_old * (zold[q] - zeta[q]) +
-                     zold[q] * alpha_old * (1.0 + sigma[q] * alpha));
-            k.alpha[q] = alpha * zn[q] / zeta[q];
-            k.zeta[q] = zn[q];
-            k.beta[q] = beta * (zn[q] / zeta[q]) * (zn[q] / zeta[q]);
-            if (!std::isfinite(zn[q])) status = COLA_BREAKDOWN;
-        }
-        if (status != COLA_OK) break;
-        COLA_HIP(h, launch_ms_update(shn, xs, ps, r64, k, st));
+        COLA_HIP(h, launch_ms_advance(state, c.slot(RHO_NEW), c.slot(PI),
+                                      full ? c.slot(PI2) : nullptr, st));
+        COLA_HIP(h, launch_ms_update(shn, xs, ps, r64, &state->coef, st));
         COLA_HIP(h, launch_cg_p(sh1, SpinorFmt::F64, SpinorFmt::F64, r64, p64, c.slot(RHO_NEW),
                                 c.slot(RHO), h->active, st));
         COLA_TRY(rotate_rho(c));
-        zold = zeta;
-        zeta = zn;
-        alpha_old = alpha;
-        beta_old = beta;
-        rho = rho_new;
         ++it;
-        for (int q = 0; q < nshift; ++q)
-            if (zeta[q] * zeta[q] * rho <= thr) done[q] = 1;
+        if (it % check == 0 || it >= p->max_iter) {
+            COLA_HIP(h, hipMemcpyAsync(flags, &state->status, sizeof flags,
+                                       hipMemcpyDeviceToHost, st));
+            COLA_HIP(h, hipStreamSynchronize(st));
+            // flags: status, finished, iterations
+            if (flags[0] != COLA_OK) {
+                status = flags[0];
+                break;
+            }
+            finished = flags[1] != 0;
+        }
     }
+    iters = finished ? flags[2] : it;
     // true residuals |b - (A + sigma_q) x_q| / |b|, all shifts in one multi-rhs pass
     std::vector<double> tr(nshift, 0.0);
     COLA_TRY(normal(cn, COLA_FP64, axs, xs));
@@ -849,7 +835,7 @@ int cg_multishift_impl(cola_handle_t *h, void *x, const void *b, int nshift, con
     COLA_HIP(h, hipStreamSynchronize(st));
     if (res) {
         res->status = status;
-        res->iterations = it;
+        res->iterations = iters;
         res->outer_cycles = 0;
         res->reliable_updates = 0;
         if (res->true_rel_residual)
