@@ -109,63 +109,85 @@ __device__ __forceinline__ const C *link(const C *U, uint32_t s, int mu) {
     return U + ((size_t)s * 4 + (size_t)mu) * 9;
 }
 
-__global__ void __launch_bounds__(256) gauge_force_kernel(const Geom g, const C *__restrict__ U,
-                                                          C *__restrict__ F, double beta) {
-    const uint32_t V = 2u * (uint32_t)g.Vh;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < 4u * V;
-         t += gridDim.x * blockDim.x) {
-        const uint32_t s = t >> 2;
-        const int mu = (int)(t & 3u);
-        int x[4], y[4], z[4];
-        coords(g, s, x);
-        const uint32_t sp = step(g, x, mu, 1, y);  // x + mu
-        M3 A;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) A.a[i][j] = C{0.0, 0.0};
-        for (int nu = 0; nu < 4; ++nu) {
-            if (nu == mu) continue;
-            int w[4];
+// Gauge force F_mu(x) = -(beta/3) traceless part of i (W - W^H) / 2 with W = U_mu(x) A and A
+// the sum of the six staples around U_mu(x).  Three lanes per link, one per direction
+// nu != mu, each forming its upper and lower staple (six link loads, about a third of
+// the registers of one lane doing all six staples, so three times the waves hide the
+// scattered link loads); the three partial sums meet in LDS and the link's first lane
+// adds them in nu order and finishes W and F.  A block covers 64 links per pass.
+constexpr int kGfLinks = 64;
+
+__global__ void __launch_bounds__(3 * kGfLinks) gauge_force_kernel(const Geom g,
+                                                                   const C *__restrict__ U,
+                                                                   C *__restrict__ F,
+                                                                   double beta) {
+    __shared__ M3 part[3 * kGfLinks];
+    const uint32_t nlinks = 8u * (uint32_t)g.Vh;
+    const int k = threadIdx.x % 3;
+    const int lk = threadIdx.x / 3;
+    // the pass count is the same for every lane of the block (barriers inside)
+    for (uint32_t base = blockIdx.x * kGfLinks; base < nlinks; base += gridDim.x * kGfLinks) {
+        const uint32_t l = base + (uint32_t)lk;
+        const bool valid = l < nlinks;
+        const uint32_t s = l >> 2;
+        const int mu = (int)(l & 3u);
+        int x[4], y[4], z[4], w[4];
+        if (valid) {
+            coords(g, s, x);
+            const uint32_t sp = step(g, x, mu, 1, y);  // x + mu
+            const int nu = k + (k >= mu ? 1 : 0);
             const uint32_t sn = step(g, x, nu, 1, w);    // x + nu
             const uint32_t sm = step(g, x, nu, -1, w);   // x - nu
             const uint32_t spm = step(g, y, nu, -1, z);  // x + mu - nu
-            // upper: U_nu(x+mu) U_mu(x+nu)^H U_nu(x)^H
-            const M3 up =
+            // upper: U_nu(x+mu) U_mu(x+nu)^H U_nu(x)^H, parked in LDS before the lower
+            // staple's loads are issued (the empty asm keeps them apart), so that one
+            // staple's matrices are live at a time
+            part[threadIdx.x] =
                 mmd(mmd(ld3(link(U, sp, nu)), ld3(link(U, sn, mu))), ld3(link(U, s, nu)));
+            asm volatile("" ::: "memory");
             // lower: U_nu(x+mu-nu)^H U_mu(x-nu)^H U_nu(x-nu)
-            const M3 a1 = ld3(link(U, spm, nu));
-            const M3 a2 = ld3(link(U, sm, mu));
-            const M3 a3 = ld3(link(U, sm, nu));
-            // a1^H a2^H a3 = (a2 a1)^H a3
-            const M3 low = mdm(mm(a2, a1), a3);
+            //     = (U_mu(x-nu) U_nu(x+mu-nu))^H U_nu(x-nu)
+            const M3 low = mdm(mm(ld3(link(U, sm, mu)), ld3(link(U, spm, nu))),
+                               ld3(link(U, sm, nu)));
+            M3 &st = part[threadIdx.x];
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
                 for (int j = 0; j < 3; ++j)
-                    A.a[i][j] = {A.a[i][j].x + up.a[i][j].x + low.a[i][j].x,
-                                 A.a[i][j].y + up.a[i][j].y + low.a[i][j].y};
+                    st.a[i][j] = {st.a[i][j].x + low.a[i][j].x, st.a[i][j].y + low.a[i][j].y};
         }
-        const M3 W = mm(ld3(link(U, s, mu)), A);
-        // X = i (W - W^H) / 2, traceless, times -(beta / 3)
-        M3 X;
+        __syncthreads();
+        if (valid && k == 0) {
+            M3 A;
+            const M3 &p0 = part[threadIdx.x], &p1 = part[threadIdx.x + 1], &p2 = part[threadIdx.x + 2];
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+            for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const C d = {W.a[i][j].x - W.a[j][i].x, W.a[i][j].y + W.a[j][i].y};
-                X.a[i][j] = {-0.5 * d.y, 0.5 * d.x};  // i d / 2
+                for (int j = 0; j < 3; ++j)
+                    A.a[i][j] = {(p0.a[i][j].x + p1.a[i][j].x) + p2.a[i][j].x,
+                                 (p0.a[i][j].y + p1.a[i][j].y) + p2.a[i][j].y};
+            const M3 W = mm(ld3(link(U, s, mu)), A);
+            // X = i (W - W^H) / 2, traceless, times -(beta / 3)
+            M3 X;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const C d = {W.a[i][j].x - W.a[j][i].x, W.a[i][j].y + W.a[j][i].y};
+                    X.a[i][j] = {-0.5 * d.y, 0.5 * d.x};  // i d / 2
+                }
+            const double tr = (X.a[0][0].x + X.a[1][1].x + X.a[2][2].x) / 3.0;
+            const double f = -beta / 3.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                X.a[i][i].x -= tr;
+                X.a[i][i].y = 0.0;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) X.a[i][j] = {f * X.a[i][j].x, f * X.a[i][j].y};
             }
-        const double tr = (X.a[0][0].x + X.a[1][1].x + X.a[2][2].x) / 3.0;
-        const double f = -beta / 3.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            X.a[i][i].x -= tr;
-            X.a[i][i].y = 0.0;
-#pragma unroll
-            for (int j = 0; j < 3; ++j) X.a[i][j] = {f * X.a[i][j].x, f * X.a[i][j].y};
+            st3(F + (size_t)l * 9, X);
         }
-        st3(F + (size_t)t * 9, X);
+        __syncthreads();  // part is reused by the next pass
     }
 }
 
@@ -441,7 +463,9 @@ int grid_for(size_t n) {
 hipError_t launch_gauge_force(const Geom &g, const void *U, void *F, double beta,
                               hipStream_t st) {
     const size_t n = (size_t)8 * g.Vh;
-    hipLaunchKernelGGL(gauge_force_kernel, dim3(grid_for(n)), dim3(256), 0, st, g,
+    const size_t blocks = (n + kGfLinks - 1) / kGfLinks;
+    const int grid = (int)std::max<size_t>(1, std::min<size_t>(blocks, 65536));
+    hipLaunchKernelGGL(gauge_force_kernel, dim3(grid), dim3(3 * kGfLinks), 0, st, g,
                        (const C *)U, (C *)F, beta);
     return hipGetLastError();
 }
