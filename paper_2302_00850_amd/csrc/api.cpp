@@ -54,6 +54,9 @@ void free_all(cola_handle_t *h) {
         hipEventDestroy(pr.second);
     }
     for (auto e : h->event_pool) hipEventDestroy(e);
+    graphs_clear(h);
+    if (h->gevent) hipEventDestroy(h->gevent), h->gevent = nullptr;
+    if (h->gstream) hipStreamDestroy(h->gstream), h->gstream = nullptr;
 }
 
 }  // namespace

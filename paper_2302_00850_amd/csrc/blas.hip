@@ -379,6 +379,10 @@ __global__ void scalar_add_kernel(double *a, const double *b, int n) {
     const int i = (int)threadIdx.x;
     if (i < n) a[i] += b[i];
 }
+__global__ void scalar_copy_kernel(double *a, const double *b, int n) {
+    const int i = (int)threadIdx.x;
+    if (i < n) a[i] = b[i];
+}
 }  // namespace
 
 hipError_t launch_ms_update(const BlasShape &sh, void *x, void *p, const void *r,
@@ -504,6 +508,12 @@ hipError_t launch_ms_residual(const BlasShape &sh, const void *b, const void *ax
 
 hipError_t launch_scalar_add(double *a, const double *b, int n, hipStream_t st) {
     hipLaunchKernelGGL(scalar_add_kernel, dim3(1), dim3(64), 0, st, a, b, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scalar_copy(double *a, const double *b, int n, hipStream_t st) {
+    if (n < 0 || n > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(scalar_copy_kernel, dim3(1), dim3(64), 0, st, a, b, n);
     return hipGetLastError();
 }
 

@@ -86,6 +86,12 @@ struct cola_handle {
     // autotuning
     int tune_mode = 0;
     std::map<std::string, cola::TuneEntry> tune;
+
+    // CG iteration blocks of small solves captured as HIP graphs, by everything their
+    // launches bake in (vectors, fields, shape); a side stream for capture and replay
+    std::map<std::string, hipGraphExec_t> graphs;
+    hipStream_t gstream = nullptr;
+    hipEvent_t gevent = nullptr;
 };
 
 namespace cola {
@@ -93,6 +99,8 @@ namespace cola {
 constexpr int kScalSlots = 16;
 
 int set_error(cola_handle_t *h, int code, const std::string &msg);
+// drops the captured graphs (their launches hold workspace addresses)
+void graphs_clear(cola_handle_t *h);
 int hip_error(cola_handle_t *h, hipError_t e, const char *what);
 
 #define COLA_HIP(h, call)                                      \

@@ -75,6 +75,8 @@ hipError_t launch_ms_residual(const BlasShape &sh, const void *b, const void *ax
                               const double *sigma, const Reduce &red, hipStream_t st);
 // a[i] += b[i] for i < n <= 64 (per-rhs scalars)
 hipError_t launch_scalar_add(double *a, const double *b, int n, hipStream_t st);
+// a[i] = b[i] for i < n <= 64
+hipError_t launch_scalar_copy(double *a, const double *b, int n, hipStream_t st);
 // x += alpha p, r -= alpha Ap, result = |r|^2 ;
 // alpha_q = active_q ? rho_q / (pi_q + pi2_q) : 0   (pi2 may be null)
 hipError_t launch_cg_xr(const BlasShape &b, SpinorFmt fx, SpinorFmt fp, SpinorFmt fr,

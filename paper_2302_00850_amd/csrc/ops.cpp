@@ -59,6 +59,7 @@ int get_vec(cola_handle_t *h, const std::string &tag, size_t bytes, void **out) 
     }
     if (it != h->cache.bufs.end()) {
         COLA_HIP(h, hipDeviceSynchronize());
+        graphs_clear(h);  // captured launches may hold the old address
         COLA_HIP(h, hipFree(it->second.first));
         h->cache.bufs.erase(it);
     }

@@ -287,3 +287,25 @@ def test_pseudofermion_action_autograd(fields):
     assert abs(S.item() - np.vdot(eta, eta).real) <= 1e-9 * abs(S_ref)
     G_ref = oracle.force(U, X, Y, KAPPA, ANTI, mode=0)
     assert rel(Ut.grad.cpu().numpy(), G_ref) <= 1e-8
+
+
+@pytest.mark.parametrize("scheme", [cola.COLA_CG_FP64, cola.COLA_CG_FP32_RELIABLE,
+                                    cola.COLA_CG_FP16_DEFECT, cola.COLA_CG_FP32_DEFECT])
+@pytest.mark.parametrize("system", [cola.COLA_SYS_MDAGM, cola.COLA_SYS_SCHUR])
+def test_captured_iteration_blocks_match_direct_launches(fields, scheme, system, monkeypatch):
+    """With COLA_GRAPHS=1 small solves replay their iteration blocks as HIP graphs: three
+    solves in a row (each replaying the graphs captured by the first, with the solver's own
+    direct launches and host reads between the replays) give bitwise the solution and
+    iteration count of the same solve launched kernel by kernel."""
+    U, b = fields
+    src = b[:3] if scheme != cola.COLA_CG_FP64 else b[:1]
+    lat = _lat(U, ANTI)
+    monkeypatch.setenv("COLA_GRAPHS", "0")
+    x0, i0 = lat.cg(_cuda(src), system=system, scheme=scheme, tol=1e-10)
+    assert i0["status"] == cola.COLA_OK, i0
+    monkeypatch.setenv("COLA_GRAPHS", "1")
+    for _ in range(3):
+        x1, i1 = lat.cg(_cuda(src), system=system, scheme=scheme, tol=1e-10)
+        assert i1["status"] == cola.COLA_OK and i1["iterations"] == i0["iterations"], (i0, i1)
+        assert torch.equal(x1, x0)
+    lat.close()
