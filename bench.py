@@ -537,7 +537,7 @@ def main():
                          "first warmup tunes every hop shape the solve uses)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(domain decomposition is a design, not built)", file=sys.stderr)
         sys.exit(2)
     if args.mode == "hop":
