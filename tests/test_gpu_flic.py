@@ -95,6 +95,24 @@ def test_flic_propagator_solve(fields, scheme, csw):
         assert r <= 1.1e-11, (q, r)  # the full-lattice residual meets tol
 
 
+def test_flic_block_cg_propagators(fields):
+    """Block CG (FP32 inner, FP64 defect correction) on the FLIC propagator system: the
+    oracle's FLIC operator applied to x gives b back to the tolerance."""
+    U, F, psi = fields
+    kappa = 0.118
+    lat = cola.Lattice(DIMS, kappa, ANTI, 1.0)
+    lat.set_gauge(_cuda(U))
+    lat.set_fat_gauge(_cuda(F))
+    b = psi[:4]
+    x, info = lat.cg(_cuda(b), system=cola.COLA_SYS_PROPAGATOR, scheme=cola.COLA_CG_FP32_DEFECT,
+                     tol=1e-10, block=1)
+    assert info["status"] == cola.COLA_OK, info
+    xs = x.cpu().numpy()
+    for q in range(4):
+        r = rel(flic.apply_flic(U, F, xs[q], kappa, ANTI, csw=1.0), b[q])
+        assert r <= 1.1e-10, (q, r)
+
+
 def test_flic_normal_cg_and_return_to_wilson(fields):
     U, F, psi = fields
     kappa = 0.12

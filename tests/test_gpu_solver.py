@@ -118,6 +118,24 @@ def test_block_cg_reaches_tolerance(fields, scheme, system):
     assert rel(xs, x2.cpu().numpy()) < 1e-7
 
 
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 8, 16])
+def test_block_cg_column_counts(fields, nrhs):
+    """Block CG with 1 to 16 columns (the unit kernels' partial wavefronts and every Gram
+    row count): each column's normal-system residual, recomputed by the oracle, meets the
+    tolerance."""
+    U, _ = fields
+    s = Synth(303 + nrhs)
+    src = s.gaussian_spinor(DIMS, nrhs).numpy()
+    lat = _lat(U, ANTI)
+    x, info = lat.cg(_cuda(src), system=cola.COLA_SYS_SCHUR, scheme=cola.COLA_CG_FP32_DEFECT,
+                     tol=1e-10, block=1)
+    assert info["status"] == cola.COLA_OK, info
+    xs = x.cpu().numpy()
+    for q in range(nrhs):
+        r = _normal_residual(U, xs[q], src[q], cola.COLA_SYS_SCHUR, KAPPA, ANTI)
+        assert r <= 1.05e-10, (nrhs, q, r)
+
+
 def test_block_cg_dependent_columns(fields):
     """Duplicate and zero columns make the block Gram matrices singular; the
     deflating small solve must still converge every column."""
