@@ -105,6 +105,29 @@ int lincomb(const Eig &e, void *out, cd a, const std::vector<const void *> &V,
     return COLA_OK;
 }
 
+// out = a out + sum_j c_j V_j, and |out|^2 into result slot 0 (no wait)
+int lincomb_norm(const Eig &e, void *out, cd a, const std::vector<const void *> &V,
+                 const std::vector<cd> &c) {
+    const size_t m = V.size();
+    size_t j0 = 0;
+    do {
+        const int k = (int)std::min<size_t>(kEigChunk, m - j0);
+        EigVecs vv{};
+        EigCoef cc{};
+        for (int j = 0; j < k; ++j) {
+            vv.v[j] = (const Cplx64 *)V[j0 + j];
+            cc.c[j] = {c[j0 + j].real(), c[j0 + j].imag()};
+        }
+        const cd aa = j0 == 0 ? a : cd(1, 0);
+        const bool last = j0 + (size_t)k >= m;
+        COLA_HIP(e.h, launch_eig_lincomb(out, aa.real(), aa.imag(), vv, cc, k, e.n, e.st,
+                                         last ? e.h->partial : nullptr,
+                                         last ? e.dres : nullptr));
+        j0 += (size_t)k;
+    } while (j0 < m);
+    return COLA_OK;
+}
+
 int copy(const Eig &e, void *dst, const void *src) {
     COLA_HIP(e.h, hipMemcpyAsync(dst, src, e.bytes, hipMemcpyDeviceToDevice, e.st));
     return COLA_OK;
@@ -205,15 +228,20 @@ int eigensolve_impl(cola_handle_t *h, void *Xc, int nv, const cola_eig_params_t 
             // Host waits per step: five (the two projections, the products with z, the
             // renormalisation, |g|^2).  Projecting q off X_0..X_{i-1} and x in one pass
             // equals doing it one after the other, x being orthogonal to the X_j; q and z
-            // are used unnormalised, with |q| taken from the same wait as <x, z>, <q, z>.
+            // are used unnormalised, with |q| taken from the same wait as <x, z>, <q, z>;
+            // the line-search update, the renormalisation and the gradient run as fused
+            // passes (eig_rotate, eig_scale_grad), |g|^2 in the projection's pass.
             std::vector<const void *> Vx(X.begin(), X.begin() + i);
             Vx.push_back(x);
+            // q = pv less its components along Vx, formed in one pass from pv
+            std::vector<const void *> Vq(Vx);
+            Vq.insert(Vq.begin(), pv);
             for (int it = 0; it < inner_max; ++it) {
                 if (!(gn2 > 0.0)) break;
-                COLA_TRY(copy(e, q, pv));
-                COLA_TRY(dots(e, Vx, q, d));
+                COLA_TRY(dots(e, Vx, pv, d));
                 for (auto &c : d) c = -c;
-                COLA_TRY(lincomb(e, q, cd(1, 0), Vx, d));
+                d.insert(d.begin(), cd(1, 0));
+                COLA_TRY(lincomb(e, q, cd(0, 0), Vq, d));
                 COLA_TRY(apply_A(e, z, q));
                 ++napply;
                 COLA_TRY(dots_at(e, {x, q}, z, 0));
@@ -224,18 +252,26 @@ int eigensolve_impl(cola_handle_t *h, void *Xc, int nv, const cola_eig_params_t 
                 // with q^ = q / |q|, z^ = z / |q|: <x, z^> = d0 / |q|, <q^, z^> = d1 / |q|^2
                 cd u0, u1;
                 lower_eigvec(mu, d[0] / qn, d[1].real() / (qn * qn), &u0, &u1);
-                COLA_TRY(lincomb(e, x, u0, {q}, {u1 / qn}));
-                COLA_TRY(lincomb(e, y, u0, {z}, {u1 / qn}));
-                COLA_TRY(dots_at(e, {x}, x, 0));
-                COLA_TRY(dots_at(e, {x}, y, 1));
+                // x = u0 x + u1 q^, y = u0 y + u1 z^, with |x|^2 and <x, y> in the same pass
+                const cd cq = u1 / qn;
+                COLA_HIP(h, launch_eig_rotate(x, y, q, z, {u0.real(), u0.imag()},
+                                              {cq.real(), cq.imag()}, e.n, h->partial, e.dres,
+                                              st));
                 COLA_TRY(read_dots(e, 2, d));
                 nx = std::sqrt(std::max(0.0, d[0].real()));
-                COLA_TRY(lincomb(e, x, cd(1 / nx, 0), {}, {}));
-                COLA_TRY(lincomb(e, y, cd(1 / nx, 0), {}, {}));
                 mu = d[1].real() / (nx * nx);
-                COLA_TRY(lincomb(e, g, cd(0, 0), {y, x}, {cd(1, 0), cd(-mu, 0)}));
-                COLA_TRY(project(e, X, i, g));
-                COLA_TRY(dots(e, {g}, g, d));
+                // renormalise x, y and form the gradient g = y - mu x in one pass
+                COLA_HIP(h, launch_eig_scale_grad(x, y, g, 1 / nx, mu, e.n, st));
+                // g off X_0..X_{i-1}, |g|^2 from the same pass
+                std::vector<const void *> Vi(X.begin(), X.begin() + i);
+                if (i > 0) {
+                    COLA_TRY(dots(e, Vi, g, d));
+                    for (auto &c : d) c = -c;
+                } else {
+                    d.clear();
+                }
+                COLA_TRY(lincomb_norm(e, g, cd(1, 0), Vi, d));
+                COLA_TRY(read_dots(e, 1, d));
                 const double gnew2 = d[0].real();
                 if (!std::isfinite(gnew2))
                     return breakdown("non-finite gradient");

@@ -134,9 +134,18 @@ struct EigCoef {
 // result[2j], result[2j+1] = Re, Im <V_j, w> for j < k <= kEigChunk (partial: handle buffer)
 hipError_t launch_eig_dots(const EigVecs &V, int k, const void *w, size_t n, double *partial,
                            double *result, hipStream_t st);
-// out = a out + sum_{j<k} c_j V_j (a = 0: out is not read; out may be one of the V_j)
+// out = a out + sum_{j<k} c_j V_j (a = 0: out is not read; out may be one of the V_j);
+// with result non-null also result[0] = |out|^2, result[1] = 0 (after the update)
 hipError_t launch_eig_lincomb(void *out, double are, double aim, const EigVecs &V,
-                              const EigCoef &c, int k, size_t n, hipStream_t st);
+                              const EigCoef &c, int k, size_t n, hipStream_t st,
+                              double *partial = nullptr, double *result = nullptr);
+// x = u x + c q, y = u y + c z (u, c complex), then result[0] = |x|^2, result[1] = 0,
+// result[2], result[3] = Re, Im <x, y>
+hipError_t launch_eig_rotate(void *x, void *y, const void *q, const void *z, Cplx64 u, Cplx64 c,
+                             size_t n, double *partial, double *result, hipStream_t st);
+// x *= s, y *= s, g = y - mu x (s, mu real)
+hipError_t launch_eig_scale_grad(void *x, void *y, void *g, double s, double mu, size_t n,
+                                 hipStream_t st);
 
 // --- clover
 // Builds A = 1 - kappa csw sum sigma F (two 6x6 chiral blocks) and A^-1 per site from
