@@ -100,10 +100,11 @@ struct HopArgs {
     int sites_per_block; // T: threads per block = T * groups
     int tchunk;          // timeslices one lane walks (t-streaming); divides Lt
     FastDiv div_ncol;    // division by the checkerboard sites of one timeslice
-    // spatial tiling (tile_y > 0): work ordered (tile, t, column in tile); a tile is
-    // all x-rows of tile_y x tile_z (y, z) columns
+    // spatial tiling (tile_y > 0): work ordered (tile, time chunk, column in tile); a
+    // tile is all x-rows of tile_y x tile_z (y, z) columns; div_nk divides by the time
+    // chunks Lt / tchunk
     int tile_y, tile_z;
-    FastDiv div_tcols, div_lt, div_lxh, div_ty, div_nty;
+    FastDiv div_tcols, div_nk, div_lxh, div_ty, div_nty;
     // the site's links staged in LDS by its first eight lanes (groups >= 8, one rhs per
     // lane, sites_per_block <= 32, 12-real FP16 / FP32 links)
     int stage_links;

@@ -22,6 +22,16 @@
 // and |out|^2 per rhs can be accumulated: per-block partials, summed in block
 // order by a reduce_partials launch that follows.
 //
+// Time walk (FP32 spinors, one rhs per lane, links staged in LDS): a lane keeps the same
+// (xh, y, z) and walks the timeslices of its chunk.  The input sites with the lane's own
+// checkerboard index at t - 1, t and t + 1 are its two time neighbours and one of its
+// two x neighbours, and each of them is needed again one or two steps later, so they
+// stay in registers: a step loads the t + 1 site and the other x, y and z neighbours
+// (six spinors instead of eight), and the reuse that otherwise depends on a site staying
+// in L2 for a whole step of the walk is certain.  These kernels run at three waves per
+// SIMD to hold the extra spinors.  Every kernel adds the eight directions in the same
+// order (t backward first), so all launch shapes give bitwise the same result.
+//
 // FL (the fat-link irrelevant clover operator): the hop of direction mu is
 // (F - g_mu U) psi(x+mu) forward and (F^H + g_mu U^H) psi(x-mu) backward, with U the
 // thin links (a.gauge) and F the smeared links (a.gauge_fat).  Writing
@@ -70,6 +80,20 @@ __device__ __forceinline__ void hop_fetch(const HopArgs &a, const SpinorBlock<SF
         }
     }
 }
+
+// the spinor of site n (rhs j) into f: one rhs per lane, FP32 / FP64 blocks
+template <SpinorFmt SF>
+__device__ __forceinline__ void fetch_site(const SpinorBlock<SF, true> &in, uint32_t n, uint32_t j,
+                                           Fetched<SF, 1> &f) {
+    f.n = n;
+    typename SpinorT<SF>::real one;
+    in.load_unscaled(n, j, f.s[0], &one);
+}
+
+// The order in which the eight directions d = 2 mu + dir are added: t backward first,
+// then x, y, z and t forward (the time walk has the t backward neighbour in registers
+// at the start of a step).
+constexpr int hop_order(int k) { return k == 0 ? 7 : k - 1; }
 
 // One of the eight hopping directions (MU, DIR) added into the accumulators of the
 // lane's RPT right-hand sides at checkerboard site i (coordinates x), from the fetched
@@ -195,11 +219,22 @@ __device__ __forceinline__ void hop_dir(const HopArgs &a, int p, uint32_t i, con
         for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(acc[r][c].x), "+v"(acc[r][c].y));
 }
 
+// the kernels that walk time with neighbours in registers (not with the CG-update
+// epilogues, whose x, p and r would not fit beside them)
+template <SpinorFmt SF, int RPT, int EPI, bool SHL, bool FL>
+constexpr bool hop_walks() {
+    return SF == SpinorFmt::F32 && RPT == 1 && SHL && !FL && EPI != EPI_XPAY_CG &&
+           EPI != EPI_CLOV_XPAY_CG;
+}
+
 template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, int EPI, bool RPH, bool SHL,
           bool FL = false>
-__global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(hop_walks<SF, RPT, EPI, SHL, FL>() ? 3 : 1)))
+    hop_kernel(const HopArgs a) {
     using T = typename SpinorT<SF>::real;
     using C = cpx<T>;
+    constexpr bool WALK = hop_walks<SF, RPT, EPI, SHL, FL>();
     extern __shared__ double red[];
     // SHL: the site's eight links staged in LDS by its first eight lanes, and with a clover
     // epilogue (FP32 blocks) the site's clover block by all its lanes
@@ -233,7 +268,9 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     // timeslices: the spinors its t-neighbours need were fetched one step earlier.  The
     // trip count is the same for every lane of a block (lanes past the end idle), so the
     // staging barriers are reached by all.
-    for (uint32_t ch = cfirst; ch < c1; ch += cstep)
+    for (uint32_t ch = cfirst; ch < c1; ch += cstep) {
+    // WALK: the input sites of the lane's index at t - 1, t, t + 1
+    Fetched<SF, 1> rp, rc, rn;
     for (int tt = 0; tt < a.tchunk; ++tt) {
         const uint32_t w = ch * blockDim.x + threadIdx.x;
         const bool valid = w < a.total;
@@ -241,11 +278,13 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
         const uint32_t j = w - q * (uint32_t)a.groups;
         uint32_t i;
         if (a.tile_y > 0) {
-            // q = (tile * Lt + t) * tile_cols + col; col = xh + Lxh (yl + tile_y zl)
+            // q = (tile * nk + k) * tile_cols + col; col = xh + Lxh (yl + tile_y zl); the
+            // lane walks t = k tchunk + tt (nk = Lt / tchunk time chunks per tile)
             const uint32_t rest = fdiv(q, a.div_tcols);
             const uint32_t col = q - rest * (uint32_t)(g.Lxh * a.tile_y * a.tile_z);
-            const uint32_t tile = fdiv(rest, a.div_lt);
-            const uint32_t t = rest - tile * (uint32_t)g.L[3];
+            const uint32_t tile = fdiv(rest, a.div_nk);
+            const uint32_t kc = rest - tile * ((uint32_t)g.L[3] / (uint32_t)a.tchunk);
+            const uint32_t t = kc * (uint32_t)a.tchunk + (uint32_t)tt;
             const uint32_t r1 = fdiv(col, a.div_lxh);
             const uint32_t xh = col - r1 * (uint32_t)g.Lxh;
             const uint32_t zl = fdiv(r1, a.div_ty);
@@ -290,24 +329,72 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) acc[r][c] = {(T)0, (T)0};
 
-        // directions computed one behind their fetch (two buffers, A and B)
-        Fetched<SF, RPT> fa, fb;
-        hop_fetch<0, 0, SF, RPT>(a, in, i, x, j, fa);
-        hop_fetch<0, 1, SF, RPT>(a, in, i, x, j, fb);
-        hop_dir<0, 0, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fa);
-        hop_fetch<1, 0, SF, RPT>(a, in, i, x, j, fa);
-        hop_dir<0, 1, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fb);
-        hop_fetch<1, 1, SF, RPT>(a, in, i, x, j, fb);
-        hop_dir<1, 0, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fa);
-        hop_fetch<2, 0, SF, RPT>(a, in, i, x, j, fa);
-        hop_dir<1, 1, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fb);
-        hop_fetch<2, 1, SF, RPT>(a, in, i, x, j, fb);
-        hop_dir<2, 0, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fa);
-        hop_fetch<3, 0, SF, RPT>(a, in, i, x, j, fa);
-        hop_dir<2, 1, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fb);
-        hop_fetch<3, 1, SF, RPT>(a, in, i, x, j, fb);
-        hop_dir<3, 0, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fa);
-        hop_dir<3, 1, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fb);
+        if constexpr (WALK) {
+            // a step of the time walk: rp and rc carried over (loaded at the first step),
+            // the x neighbour that is not site i and the y, z neighbours through f0 / rp,
+            // rn (t + 1) loaded for this step and kept for the next two
+            const bool bx = (x[0] & 1) != 0;  // x = 2 xh + bx: site i is the x neighbour
+            Fetched<SF, 1> f0;
+            if (tt == 0) {
+                fetch_site<SF>(in, nb_bwd(g, i, x, 3), j, rp);
+                fetch_site<SF>(in, i, j, rc);
+            }
+            fetch_site<SF>(in, bx ? nb_fwd(g, i, x, 0) : nb_bwd(g, i, x, 0), j, f0);
+            fetch_site<SF>(in, nb_fwd(g, i, x, 3), j, rn);
+            hop_dir<3, 1, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, rp);
+            fetch_site<SF>(in, nb_fwd(g, i, x, 1), j, rp);
+            // in place: rc <- the forward x neighbour, f0 <- the backward one (undone below)
+            auto swap_x = [&]() {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    const C u = f0.s[0][c], v = rc.s[0][c];
+                    f0.s[0][c] = bx ? v : u;
+                    rc.s[0][c] = bx ? u : v;
+                }
+                const uint32_t nu = f0.n, nv = rc.n;
+                f0.n = bx ? nv : nu;
+                rc.n = bx ? nu : nv;
+            };
+            rc.n = i;
+            swap_x();
+            hop_dir<0, 0, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, rc);
+            hop_dir<0, 1, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, f0);
+            swap_x();
+            fetch_site<SF>(in, nb_bwd(g, i, x, 1), j, f0);
+            hop_dir<1, 0, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, rp);
+            fetch_site<SF>(in, nb_fwd(g, i, x, 2), j, rp);
+            hop_dir<1, 1, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, f0);
+            fetch_site<SF>(in, nb_bwd(g, i, x, 2), j, f0);
+            hop_dir<2, 0, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, rp);
+            hop_dir<2, 1, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, f0);
+            hop_dir<3, 0, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, rn);
+            // the next step's t - 1 and t sites (its t + 1 site follows t + 1 here)
+            rp = rc;
+            rc = rn;
+        } else {
+            // directions computed one behind their fetch (two buffers, A and B), in the
+            // order hop_order
+            constexpr int d0 = hop_order(0), d1 = hop_order(1), d2 = hop_order(2),
+                          d3 = hop_order(3), d4 = hop_order(4), d5 = hop_order(5),
+                          d6 = hop_order(6), d7 = hop_order(7);
+            Fetched<SF, RPT> fa, fb;
+            hop_fetch<d0 / 2, d0 % 2, SF, RPT>(a, in, i, x, j, fa);
+            hop_fetch<d1 / 2, d1 % 2, SF, RPT>(a, in, i, x, j, fb);
+            hop_dir<d0 / 2, d0 % 2, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fa);
+            hop_fetch<d2 / 2, d2 % 2, SF, RPT>(a, in, i, x, j, fa);
+            hop_dir<d1 / 2, d1 % 2, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fb);
+            hop_fetch<d3 / 2, d3 % 2, SF, RPT>(a, in, i, x, j, fb);
+            hop_dir<d2 / 2, d2 % 2, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fa);
+            hop_fetch<d4 / 2, d4 % 2, SF, RPT>(a, in, i, x, j, fa);
+            hop_dir<d3 / 2, d3 % 2, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fb);
+            hop_fetch<d5 / 2, d5 % 2, SF, RPT>(a, in, i, x, j, fb);
+            hop_dir<d4 / 2, d4 % 2, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fa);
+            hop_fetch<d6 / 2, d6 % 2, SF, RPT>(a, in, i, x, j, fa);
+            hop_dir<d5 / 2, d5 % 2, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fb);
+            hop_fetch<d7 / 2, d7 % 2, SF, RPT>(a, in, i, x, j, fb);
+            hop_dir<d6 / 2, d6 % 2, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fa);
+            hop_dir<d7 / 2, d7 % 2, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, fb);
+        }
 
         const T ca = (T)a.a;
         constexpr bool CG = EPI == EPI_XPAY_CG || EPI == EPI_CLOV_XPAY_CG;
@@ -385,6 +472,7 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
                 nrm[r] += s;
             }
         }
+    }
     }
     if (a.want_norm) {
         const int slot = threadIdx.x / a.groups;

@@ -211,7 +211,10 @@ def test_hop_identical_across_launch_shapes(fields, prec, monkeypatch):
 
 STAGED = ["1,16,0,1,0,0,1", "1,16,0,1,2,2,1", "1,8,7,1,0,0,1", "1,16,3,2,0,0,1",
           "1,16,0,5,0,0,1", "1,32,0,1,2,4,1", "1,16,-1,1,2,2,1", "2,32,0,1,0,0,1",
-          "2,16,5,1,2,2,1", "2,32,0,2,0,0,1"]
+          "2,16,5,1,2,2,1", "2,32,0,2,0,0,1",
+          # tiles walked in time chunks (FP32: neighbours carried in registers)
+          "1,16,0,2,2,2,1", "1,16,0,5,2,4,1", "1,16,3,2,2,2,1", "1,8,-1,10,4,4,1",
+          "2,16,0,5,2,2,1"]
 
 
 @pytest.mark.parametrize("prec", [2, 3])
@@ -219,8 +222,9 @@ STAGED = ["1,16,0,1,0,0,1", "1,16,0,1,2,2,1", "1,8,7,1,0,0,1", "1,16,3,2,0,0,1",
 def test_staged_links_identical(fields, prec, op, monkeypatch):
     """With 12 rhs the lanes of a site can stage its links in LDS; the result is bitwise
     the one of per-lane link loads, for several block sizes, grid-stride loops with a
-    ragged last pass, time chunks and tiles (and with the fused norm and clover
-    epilogues of the Schur operator)."""
+    ragged last pass, time chunks and tiles, tiles walked in time chunks (the FP32 time
+    walk with neighbours in registers), and with the fused norm and clover epilogues of
+    the Schur operator."""
     U, psi = fields
     nrhs = 12
     clover = op == "clover_schur"
