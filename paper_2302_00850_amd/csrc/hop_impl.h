@@ -22,14 +22,15 @@
 // and |out|^2 per rhs can be accumulated: per-block partials, summed in block
 // order by a reduce_partials launch that follows.
 //
-// Time walk (FP32 spinors, one rhs per lane, links staged in LDS): a lane keeps the same
+// Time walk (one rhs per lane, links staged in LDS): a lane keeps the same
 // (xh, y, z) and walks the timeslices of its chunk.  The input sites with the lane's own
 // checkerboard index at t - 1, t and t + 1 are its two time neighbours and one of its
 // two x neighbours, and each of them is needed again one or two steps later, so they
 // stay in registers: a step loads the t + 1 site and the other x, y and z neighbours
 // (six spinors instead of eight), and the reuse that otherwise depends on a site staying
-// in L2 for a whole step of the walk is certain.  These kernels run at three waves per
-// SIMD to hold the extra spinors.  Every kernel adds the eight directions in the same
+// in L2 for a whole step of the walk is certain.  These kernels (FP32 and FP16, used when
+// a lane walks more than one timeslice) run at three waves per SIMD to hold the extra
+// spinors.  Every kernel adds the eight directions in the same
 // order (t backward first), so all launch shapes give bitwise the same result.
 //
 // FL (the fat-link irrelevant clover operator): the hop of direction mu is
@@ -81,13 +82,17 @@ __device__ __forceinline__ void hop_fetch(const HopArgs &a, const SpinorBlock<SF
     }
 }
 
-// the spinor of site n (rhs j) into f: one rhs per lane, FP32 / FP64 blocks
+// the spinor of site n (rhs j) into f, one rhs per lane (FP16: raw halves and scale)
 template <SpinorFmt SF>
 __device__ __forceinline__ void fetch_site(const SpinorBlock<SF, true> &in, uint32_t n, uint32_t j,
                                            Fetched<SF, 1> &f) {
     f.n = n;
-    typename SpinorT<SF>::real one;
-    in.load_unscaled(n, j, f.s[0], &one);
+    if constexpr (SF == SpinorFmt::F16) {
+        in.template load_raw_h2_group<1>(n, j, f.s, f.scl);
+    } else {
+        typename SpinorT<SF>::real one;
+        in.load_unscaled(n, j, f.s[0], &one);
+    }
 }
 
 // The order in which the eight directions d = 2 mu + dir are added: t backward first,
@@ -219,22 +224,24 @@ __device__ __forceinline__ void hop_dir(const HopArgs &a, int p, uint32_t i, con
         for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(acc[r][c].x), "+v"(acc[r][c].y));
 }
 
-// the kernels that walk time with neighbours in registers (not with the CG-update
-// epilogues, whose x, p and r would not fit beside them)
+// The kernels that can walk time with neighbours in registers: FP32 and FP16 spinors,
+// one rhs per lane, staged links, not the CG-update epilogues (whose x, p and r would
+// not fit beside the carried spinors).  They walk (a second instantiation, WK) when a
+// lane has more than one timeslice to walk.
 template <SpinorFmt SF, int RPT, int EPI, bool SHL, bool FL>
 constexpr bool hop_walks() {
-    return SF == SpinorFmt::F32 && RPT == 1 && SHL && !FL && EPI != EPI_XPAY_CG &&
-           EPI != EPI_CLOV_XPAY_CG;
+    return (SF == SpinorFmt::F32 || SF == SpinorFmt::F16) && RPT == 1 && SHL && !FL &&
+           EPI != EPI_XPAY_CG && EPI != EPI_CLOV_XPAY_CG;
 }
 
 template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, int EPI, bool RPH, bool SHL,
-          bool FL = false>
-__global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(hop_walks<SF, RPT, EPI, SHL, FL>() ? 3 : 1)))
+          bool FL = false, bool WK = false>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WK ? 3 : 1)))
     hop_kernel(const HopArgs a) {
     using T = typename SpinorT<SF>::real;
     using C = cpx<T>;
-    constexpr bool WALK = hop_walks<SF, RPT, EPI, SHL, FL>();
+    constexpr bool WALK = WK;
+    static_assert(!WK || hop_walks<SF, RPT, EPI, SHL, FL>(), "no time walk for this kernel");
     extern __shared__ double red[];
     // SHL: the site's eight links staged in LDS by its first eight lanes, and with a clover
     // epilogue (FP32 blocks) the site's clover block by all its lanes
@@ -347,10 +354,13 @@ __global__ void __launch_bounds__(256)
             auto swap_x = [&]() {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
-                    const C u = f0.s[0][c], v = rc.s[0][c];
+                    const auto u = f0.s[0][c], v = rc.s[0][c];
                     f0.s[0][c] = bx ? v : u;
                     rc.s[0][c] = bx ? u : v;
                 }
+                const float su = f0.scl[0], sv = rc.scl[0];
+                f0.scl[0] = bx ? sv : su;
+                rc.scl[0] = bx ? su : sv;
                 const uint32_t nu = f0.n, nv = rc.n;
                 f0.n = bx ? nv : nu;
                 rc.n = bx ? nu : nv;
@@ -486,6 +496,17 @@ template <SpinorFmt SF, LinkFmt LF, typename CR, int RPT, int EPI, bool RPH, boo
           bool FL = false>
 hipError_t hop_launch_t(const HopArgs &a, int grid, int block, hipStream_t st) {
     const size_t shm = a.want_norm ? (size_t)a.sites_per_block * a.nrhs * sizeof(double) : 0;
+    if constexpr (hop_walks<SF, RPT, EPI, SHL, FL>()) {
+        if (a.tchunk > 1) {
+            if (a.occupancy)
+                return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    a.occupancy, hop_kernel<SF, LF, CR, RPT, EPI, RPH, SHL, FL, true>, block,
+                    shm);
+            hipLaunchKernelGGL((hop_kernel<SF, LF, CR, RPT, EPI, RPH, SHL, FL, true>), dim3(grid),
+                               dim3(block), shm, st, a);
+            return hipGetLastError();
+        }
+    }
     if (a.occupancy)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(
             a.occupancy, hop_kernel<SF, LF, CR, RPT, EPI, RPH, SHL, FL>, block, shm);
