@@ -339,7 +339,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WK ? 3
         if constexpr (WALK) {
             // a step of the time walk: rp and rc carried over (loaded at the first step),
             // the x neighbour that is not site i and the y, z neighbours through f0 / rp,
-            // rn (t + 1) loaded for this step and kept for the next two
+            // rn (t + 1) loaded for this step and kept for the next two.  rn is loaded
+            // after the y and z neighbours: those are the t sites that other lanes loaded
+            // as their rn one step earlier, and issuing them first shortens the time such
+            // a line has to stay in L2 (measured: 1.8 GB fewer reads per launch at 48^3 x 96)
             const bool bx = (x[0] & 1) != 0;  // x = 2 xh + bx: site i is the x neighbour
             Fetched<SF, 1> f0;
             if (tt == 0) {
@@ -347,7 +350,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WK ? 3
                 fetch_site<SF>(in, i, j, rc);
             }
             fetch_site<SF>(in, bx ? nb_fwd(g, i, x, 0) : nb_bwd(g, i, x, 0), j, f0);
-            fetch_site<SF>(in, nb_fwd(g, i, x, 3), j, rn);
             hop_dir<3, 1, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, rp);
             fetch_site<SF>(in, nb_fwd(g, i, x, 1), j, rp);
             // in place: rc <- the forward x neighbour, f0 <- the backward one (undone below)
@@ -375,6 +377,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WK ? 3
             fetch_site<SF>(in, nb_fwd(g, i, x, 2), j, rp);
             hop_dir<1, 1, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, f0);
             fetch_site<SF>(in, nb_bwd(g, i, x, 2), j, f0);
+            fetch_site<SF>(in, nb_fwd(g, i, x, 3), j, rn);
             hop_dir<2, 0, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, rp);
             hop_dir<2, 1, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, f0);
             hop_dir<3, 0, SF, LF, RPT, RPH, SHL, FL>(a, p, i, x, sg_f, acc, staged, rn);
